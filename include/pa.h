@@ -1,0 +1,267 @@
+/*
+ * pa.h -- C ABI of the MI355X population-annealing library (libpa.so).
+ *
+ * Population annealing with weighted averages (J. Machta, arXiv:1006.0252) for
+ * Ising spin glasses with +-1 couplings: a population of replicas sharing one
+ * set of couplings is cooled from beta = 0 through a schedule; each step
+ * resamples the population by Boltzmann weights (Sec. II, eqs. Q and wn, Poisson
+ * copy numbers), runs theta Metropolis sweeps at the new temperature, measures
+ * observables, and accumulates the free-energy estimator (eq. sumQ).  Runs are
+ * combined by free-energy weighted averages (Sec. III, eqs. weight, omega, bestf;
+ * Sec. IV, eq. omegaprime).
+ *
+ * Conventions common to every call
+ *   - Every function returns an int status (PA_OK = 0) and never aborts; no C++
+ *     exception crosses this interface.
+ *   - The library allocates no device memory.  All device buffers are owned by the
+ *     caller, sized by pa_buffer_sizes(), and described in a pa_run.  Host pointers
+ *     are only borrowed for the duration of a call.
+ *   - Device work is asynchronous and ordered on run->stream (a hipStream_t, NULL =
+ *     the null stream).  Nothing but pa_status() and pa_query() waits for the device.
+ *     Population sizes stay on the device, so sweep/resample/measure/free-energy
+ *     calls may be captured in a HIP graph.
+ *   - Errors found on the host (bad arguments) are returned at once.  Errors found on
+ *     the device (capacity overflow, extinction, non-finite weights) set sticky bits in
+ *     the run's device state; pa_status() reads them.  A step that raises one leaves
+ *     the population unchanged.
+ *   - Calls with n_runs > 1 apply the same step to every run (batching).
+ *
+ * Physics conventions
+ *   - dim 1: periodic chain of N = L spins; bond b = i joins sites i and i+1 (mod N).
+ *     dim 3: periodic simple cubic lattice of N = L^3 spins, site i = x + L (y + L z);
+ *     bond b = 3 i + a joins site i and its +a neighbour (a = 0, 1, 2 for x, y, z).
+ *     L must be even (checkerboard order needs a bipartite lattice).
+ *   - Energy E = + sum_b J_b s_i s_j (the sign printed in Sec. IV), J_b = +-1.
+ *   - Spins: 1 means s = -1.  Layout PA_U8: one byte per spin, replica-major rows of
+ *     row_stride bytes (N rounded up to 16).  Layout PA_BITS64 (bit-packed, replicas in
+ *     groups of 64): the lattice is cut into rows -- (y, z) rows of L sites on the cube,
+ *     runs of 32 consecutive sites on the chain -- and each replica stores one W-bit row
+ *     word per row (W = 8, 16 or 32, the smallest >= L on the cube; 32 on the chain), bit x
+ *     = spin at site x + L row (cube) or 32 row + x (chain); row word (g, row, l) of replica
+ *     64 g + l is element (g * n_rows + row) * 64 + l.  An L = 16 replica takes 512 bytes.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the run seed
+ *     (couplings: by the disorder seed); counter layouts are documented at each call.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define PA_OK 0
+#define PA_ERR_ARG 1        /* invalid argument (odd L, dim not 1/3, beta_to < beta_from, ...) */
+#define PA_ERR_CAPACITY 2   /* resampled population larger than the buffers' capacity */
+#define PA_ERR_EXTINCT 3    /* resampled population empty */
+#define PA_ERR_NONFINITE 4  /* normalisation sum S not finite or not positive */
+#define PA_ERR_HIP 5        /* HIP runtime error (launch, copy, synchronisation) */
+#define PA_ERR_NOT_INIT 6   /* run not initialised by pa_init_couplings */
+
+/* sticky device status bits (pa_status) */
+#define PA_FLAG_CAPACITY (1 << 0)
+#define PA_FLAG_EXTINCT (1 << 1)
+#define PA_FLAG_NONFINITE (1 << 2)
+
+/* spin layouts */
+#define PA_U8 0
+#define PA_BITS64 1 /* bit-packed rows, groups of 64 replicas (see above) */
+
+/* Per-temperature record, one per schedule index k, written on the device.
+ * pa_resample fills beta .. E_lo of record[k]; pa_measure fills the rest. */
+typedef struct pa_record {
+    double beta;        /* beta_k */
+    double lnQ;         /* ln Q(beta_{k-1}, beta_k) (eq. Q); 0 at k = 0 */
+    double minus_betaF; /* -beta_k F~(beta_k) = N ln 2 + sum_{l <= k} ln Q_l (eq. sumQ) */
+    double S;           /* sum over energies E of h(E) exp(-(beta_k - beta_{k-1})(E - E_lo)) */
+    double R;           /* population size after resampling */
+    double E_lo;        /* lowest energy in the population before resampling */
+    double E_mean;      /* energy mean after the sweeps (no weights inside a run, Sec. II) */
+    double E_var;       /* energy variance (population, 1/R) */
+    double E_skew;      /* third central moment / var^1.5 */
+    double q2;          /* <q^2> over replica pairs with the partner run (Sec. IV) */
+    double q4;          /* <q^4> */
+    double gamma;       /* Prob(|q| < 0.2) (Sec. IV) */
+    double n_pairs;     /* replica pairs behind q2, q4, gamma (0: no partner) */
+    double reserved[3];
+} pa_record;
+
+/* Device state of one run (caller allocates sizeof(pa_state) bytes of device memory,
+ * 256-byte aligned).  Written by pa_init_couplings and the later calls; read on the
+ * host only through pa_query. */
+typedef struct pa_state {
+    /* descriptor, written by pa_init_couplings */
+    int32_t dim, L, N, z;
+    int32_t n_bonds, layout, n_bins, row_stride;
+    int64_t capacity, R0;
+    uint64_t seed, disorder_seed;
+    int8_t* J;
+    void* spins[2];
+    int32_t* energy[2];
+    int32_t* counts;
+    int64_t* offsets;
+    uint8_t* work;
+    pa_record* record;
+    int32_t n_records, E_base;
+    /* dynamic state */
+    int64_t R;      /* current population size */
+    int64_t R_new;  /* size produced by the last resampling scan */
+    int32_t cur;    /* which of spins[]/energy[] holds the population */
+    int32_t status; /* sticky PA_FLAG_* bits */
+    int32_t E_lo, E_hi;
+    int32_t k;      /* schedule index of the current temperature */
+    int32_t initialised;
+    double acc;     /* sum of ln Q so far */
+    double ln_omega;/* N ln 2 */
+    double beta;    /* current inverse temperature */
+    uint8_t pad[48];
+} pa_state;
+
+/* Host descriptor of one run; every pointer but stream is a device pointer. */
+typedef struct pa_run {
+    int32_t dim;             /* 1 or 3 */
+    int32_t L;               /* linear size (even); N = L or L^3 */
+    int32_t layout;          /* PA_U8 or PA_BITS64 */
+    int32_t n_records;       /* entries of record[] (schedule length) */
+    int64_t capacity;        /* replicas each population buffer holds; multiple of 64 */
+    int64_t R0;              /* initial population size and default target size */
+    uint64_t seed;           /* run seed */
+    uint64_t disorder_seed;  /* coupling seed */
+    int8_t* J;               /* [n_bonds] couplings */
+    void* spins[2];          /* two population buffers of spins_bytes */
+    int32_t* energy[2];      /* two [capacity] energy buffers */
+    int32_t* counts;         /* [capacity] copy numbers of the last resampling */
+    int64_t* offsets;        /* [capacity + 1] exclusive scan of counts */
+    void* work;              /* work_bytes of scratch (histograms, bin tables, scan) */
+    pa_record* record;       /* [n_records] */
+    pa_state* state;         /* one pa_state */
+    void* stream;            /* hipStream_t */
+} pa_run;
+
+/* One temperature step beta_from -> beta_to (schedule index k >= 1). */
+typedef struct pa_step {
+    double beta_from;
+    double beta_to;
+    double R_target;         /* > 0: target population R_{beta_to} for every run; <= 0: run's R0 */
+    int32_t k;               /* schedule index of beta_to */
+    int32_t n_sweeps;        /* theta: Metropolis sweeps at beta_to */
+    int64_t t0;              /* global index of the first of those sweeps */
+    const double* weights;   /* device [n_weights]: w_d = exp(-(beta_to - beta_from) * 4d) */
+    int64_t n_weights;       /* >= n_bins of every run (pa_buffer_sizes) */
+} pa_step;
+
+/* Buffer sizes (bytes) of one run. */
+typedef struct pa_sizes {
+    int64_t N, n_bonds, n_bins, row_stride;
+    int64_t J_bytes, spins_bytes, energy_bytes, counts_bytes, offsets_bytes;
+    int64_t work_bytes, record_bytes, state_bytes;
+} pa_sizes;
+
+/* Host-side information read back by pa_query (synchronises run->stream). */
+typedef struct pa_info {
+    int64_t R, R_new;
+    int32_t cur, status, E_lo, E_hi, k, initialised;
+    double acc, ln_omega, beta;
+} pa_info;
+
+/* Sizes of every buffer of a run.  Returns PA_ERR_ARG for dim not in {1, 3}, odd or
+ * too small L (1D: L >= 4; 3D: L >= 2, L <= 32), capacity not a positive multiple of 64. */
+int pa_buffer_sizes(int dim, int L, int layout, int64_t capacity, int n_records, pa_sizes* out);
+
+/* Initialise runs (Sec. II: R0 replicas at beta = 0, each uniform over the 2^N states):
+ *   couplings: J_b = -1 iff bit (b mod 128) of Philox(ctr (b/128, 0, 0, 5), key disorder_seed)
+ *              is set, unless J_host[r] (host, [n_bonds] +-1) is given for run r;
+ *   spins: spin i of replica r is bit (i mod 128) of Philox(ctr (i/128, r, 0, 1), key seed);
+ *   energies computed from the spins; R~ = R0, accumulator 0, ln Omega = N ln 2, k = 0,
+ *   record[0] written; status cleared.
+ * J_host may be NULL (all runs from their disorder seed) or an array of n_runs host
+ * pointers, each NULL or a coupling array.  R0 must not exceed capacity. */
+int pa_init_couplings(pa_run* runs, int n_runs, const int8_t* const* J_host);
+
+/* theta = step->n_sweeps Metropolis sweeps of every replica at beta = step->beta_to
+ * (Sec. II, the equilibration loop of the algorithm).  A sweep updates all sites of
+ * colour 0 then all of colour 1 (colour (x+y+z) mod 2, or i mod 2 on the chain).
+ * Flipping spin i changes the energy by dE = 4c - 2z, c = number of bonds at i with
+ * J s_i s_j = -1; the flip is accepted if dE <= 0, else with probability T64 / 2^64,
+ * T64 = floor(exp(-beta dE) 2^64), against the uniform U = (u16 << 48) | u48:
+ *   u16 = 16-bit field (h mod 8) of Philox(ctr (h/8, r, 2t+colour, 2)), h = i/2
+ *         (field f = bits 16 (f mod 2) .. of word f/2);
+ *   u48 = word0 | (word1 mod 2^16) << 32 of Philox(ctr (i, r, 2t+colour, 3));
+ * t = step->t0 + s is the global sweep index, r the replica's index in the population.
+ * Energies are updated with the spins. */
+int pa_sweep(pa_run* runs, int n_runs, const pa_step* step);
+
+/* Resample beta_from -> beta_to (Sec. II, eqs. Q and wn, Poisson copy numbers):
+ *   h(E) = replicas at energy E; E_lo = lowest energy present;
+ *   S = sum over E ascending of h(E) * w_{(E - E_lo)/4}   (FP64, in that order);
+ *   ln Q = -(beta_to - beta_from) E_lo + ln S - ln R~;  accumulator += ln Q;
+ *   copies of replica j ~ Poisson(lambda_j), lambda_j = (R_target * w_{(E_j - E_lo)/4}) / S,
+ *   drawn by the power-of-two ladder with thinning (draw d of replica j at step k is word
+ *   d mod 4 of Philox(ctr (d/4, j, k, 4), key seed));
+ *   offsets = exclusive scan of copies, R~' = total; the new population holds the copies
+ *   of replica j at offsets[j] .. offsets[j] + copies - 1 (source order).
+ * Writes record[k].beta .. E_lo.  Raises PA_FLAG_CAPACITY (R~' > capacity),
+ * PA_FLAG_EXTINCT (R~' = 0) or PA_FLAG_NONFINITE, in which case the population, the
+ * accumulator and k are left unchanged.  step->weights must hold n_bins entries for
+ * dbeta = beta_to - beta_from (pa_fill_weights). */
+int pa_resample(pa_run* runs, int n_runs, const pa_step* step);
+
+/* Observables after the sweeps (Sec. II): energy mean, variance and skewness of the
+ * population into record[k]; with partner != NULL (host array of n_runs run indices
+ * into runs[], -1 for none) also the overlap q = (1/N) sum_i s_i s'_i of replica j
+ * with replica j of the partner run for j < min(R~, R~'), giving <q^2>, <q^4> and
+ * Gamma = Prob(|q| < 0.2) (Sec. IV). */
+int pa_measure(pa_run* runs, int n_runs, const int32_t* partner);
+
+/* -beta_k F~(beta_k) = N ln 2 + sum of ln Q (eq. sumQ) of every run at its current
+ * temperature into minus_betaF_dev[r] (device, [n_runs]). */
+int pa_free_energy(const pa_run* runs, int n_runs, double* minus_betaF_dev);
+
+/* Weighted average over M runs, host FP64 (Sec. III, eqs. weight, omega, bestf):
+ *   x_r = minus_betaF[r] (+ ln R[r] when R != NULL: runs with unequal target sizes);
+ *   omega_r = exp(x_r - max x) / sum exp(x - max x);  A_bar[o] = sum_r omega_r A[r][o];
+ *   -beta F_bar = max x + ln sum exp(x - max x) - ln sum_r R[r] (R[r] = 1 when NULL);
+ *   var = sum (minus_betaF - mean)^2 / (M - 1);  mean = plain mean of minus_betaF.
+ * For overlap observables pass minus_betaF[r] = -beta (F~^(1) + F~^(2)) of pair r
+ * (eq. omegaprime).  A is [M][n_obs] row-major; omega may be NULL. */
+int pa_weighted_average(int M, const double* minus_betaF, const double* R, const double* A, int n_obs,
+                        double* A_bar, double* omega, double* minus_betaF_bar, double* var,
+                        double* mean);
+
+/* The same on the device for n_sets independent sets of M runs (set s uses
+ * minus_betaF[s*M ..], R[s*M ..], A[s*M*n_obs ..]); out is [n_sets][n_obs + 3]:
+ * A_bar[0..n_obs-1], -beta F_bar, var, mean.  All pointers are device pointers. */
+int pa_weighted_average_dev(int n_sets, int M, const double* minus_betaF, const double* R, const double* A,
+                            int n_obs, double* out, void* stream);
+
+/* Synchronise each run's stream and read its sticky status bits into host_flags[r];
+ * returns PA_OK, or the PA_ERR_* code of the first raised bit. */
+int pa_status(const pa_run* runs, int n_runs, int32_t* host_flags);
+
+/* Synchronise run->stream and copy the dynamic part of its state to the host. */
+int pa_query(const pa_run* run, pa_info* out);
+
+/* Message for a status code. */
+const char* pa_strerror(int code);
+
+/* Host tables (FP64, libm exp).  w[d] = exp(-dbeta * 4d), d < n. */
+int pa_fill_weights(double dbeta, int64_t n, double* w);
+/* T64 thresholds for classes c = 0..z at beta (dE = 4c - 2z): T[c], always[c] = 1
+ * when the move is always accepted (dE <= 0 or exp(-beta dE) >= 1). */
+int pa_thresholds(double beta, int z, uint64_t* T, uint8_t* always);
+/* Inversion table of Poisson(2^m), m in [-20, 6]: C[n] = floor(CDF(n) 2^32), last entry
+ * 2^32; returns the length through *len (at most cap entries written). */
+int pa_ladder_table(int m, uint64_t* C, int cap, int* len);
+
+/* Launch shape of the sweep kernels for later calls in this process: lanes per replica
+ * (1, 2 or 4; a replica's rows are split among that many lanes) and waves per block (1..4).
+ * (0, 0) restores the built-in choice.  Results do not depend on it (same draws, same
+ * order of acceptance tests per site); it exists for the autotuner. */
+int pa_set_sweep_config(int lanes_per_replica, int waves_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PA_H */

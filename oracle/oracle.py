@@ -56,6 +56,9 @@ def lib():
         L.orc_energy.restype = i64
         L.orc_delta_energy.argtypes = [i32, i32, P, P, i32]
         L.orc_init_population.argtypes = [i32, i32, P, u64, i64, P, P]
+        L.orc_init_range.argtypes = [i32, i32, P, u64, i64, i64, P, P]
+        L.orc_sweep_range.argtypes = [i32, i32, P, u64, f64, i64, i64, P, P, i64, i32]
+        L.orc_copy_numbers.argtypes = [u64, i64, f64, f64, f64, i64, P, P, P]
         L.orc_threshold.argtypes = [f64, i32, P]
         L.orc_threshold.restype = u64
         L.orc_met_accept.argtypes = [u64, i64, i64, i32, i32, u64]
@@ -121,6 +124,31 @@ def init_population(dim, L, J, seed, R, capacity=None):
     E = np.zeros(cap, dtype=np.int32)
     lib().orc_init_population(dim, L, _p(J), seed, R, _p(s), _p(E))
     return s, E
+
+
+def init_replicas(dim, L, J, seed, r_first, count):
+    """replicas r_first .. r_first + count - 1 of the initial population"""
+    N = num_sites(dim, L)
+    s = np.zeros((count, N), dtype=np.uint8)
+    E = np.zeros(count, dtype=np.int32)
+    lib().orc_init_range(dim, L, _p(np.ascontiguousarray(J, np.int8)), seed, r_first, count, _p(s), _p(E))
+    return s, E
+
+
+def sweep_replicas(dim, L, J, seed, beta, r_first, s, E, t0, ns):
+    """In place: ns sweeps of replicas with population indices r_first .. r_first + len(E) - 1."""
+    assert s.dtype == np.uint8 and E.dtype == np.int32 and s.flags.c_contiguous and E.flags.c_contiguous
+    lib().orc_sweep_range(dim, L, _p(np.ascontiguousarray(J, np.int8)), seed, beta, r_first, len(E), _p(s), _p(E),
+                          t0, ns)
+
+
+def copy_numbers(seed, k, beta_from, beta_to, R_target, E):
+    """Q and the Poisson copy numbers of a population with energies E: (status, counts, S, lnQ, E_lo)."""
+    E = np.ascontiguousarray(E, np.int32)
+    counts = np.zeros(len(E), dtype=np.int32)
+    out = np.zeros(3)
+    st = lib().orc_copy_numbers(seed, k, beta_from, beta_to, float(R_target), len(E), _p(E), _p(counts), _p(out))
+    return st, counts, out[0], out[1], int(out[2])
 
 
 def threshold(beta, dE):

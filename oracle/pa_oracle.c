@@ -178,17 +178,24 @@ int orc_delta_energy(int dim, int L, const int8_t* J, const uint8_t* s, int i)
 /* microstates.  Spin i of replica r is bit (i mod 128) of                    */
 /* Philox(ctr = (i/128, r, 0, 1), key = run seed).                            */
 /* ------------------------------------------------------------------------- */
-void orc_init_population(int dim, int L, const int8_t* J, uint64_t seed, int64_t R, uint8_t* s, int32_t* E)
+void orc_init_range(int dim, int L, const int8_t* J, uint64_t seed, int64_t r_first, int64_t count, uint8_t* s,
+                    int32_t* E)
 {
     int N = orc_num_sites(dim, L);
-    for (int64_t r = 0; r < R; ++r) {
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t r = r_first + q;
         for (int i = 0; i < N; ++i) {
             uint32_t out[4];
             philox_seeded((uint32_t)(i >> 7), (uint32_t)r, 0, TAG_INIT, seed, out);
-            s[r * N + i] = (uint8_t)((out[(i & 127) >> 5] >> (i & 31)) & 1);
+            s[q * N + i] = (uint8_t)((out[(i & 127) >> 5] >> (i & 31)) & 1);
         }
-        E[r] = (int32_t)orc_energy(dim, L, J, s + r * N);
+        E[q] = (int32_t)orc_energy(dim, L, J, s + q * N);
     }
+}
+
+void orc_init_population(int dim, int L, const int8_t* J, uint64_t seed, int64_t R, uint8_t* s, int32_t* E)
+{
+    orc_init_range(dim, L, J, seed, 0, R, s, E);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -241,8 +248,9 @@ int orc_met_accept(uint64_t seed, int64_t r, int64_t t, int colour, int i, uint6
 /* of one colour have no bonds among themselves, so their order is immaterial). */
 /* Global sweep index t = t0 + s enters the RNG counters.                       */
 /* ------------------------------------------------------------------------- */
-void orc_sweep(int dim, int L, const int8_t* J, uint64_t seed, double beta,
-               int64_t R, uint8_t* spins, int32_t* E, int64_t t0, int ns)
+/* replicas r_first .. r_first + count - 1 (population indices), stored from spins[0] */
+void orc_sweep_range(int dim, int L, const int8_t* J, uint64_t seed, double beta, int64_t r_first,
+                     int64_t count, uint8_t* spins, int32_t* E, int64_t t0, int ns)
 {
     int N = orc_num_sites(dim, L);
     int z = coordination(dim);
@@ -253,8 +261,9 @@ void orc_sweep(int dim, int L, const int8_t* J, uint64_t seed, double beta,
         T[dE + 2 * z] = orc_threshold(beta, dE, &always[dE + 2 * z]);
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t r = 0; r < R; ++r) {
-        uint8_t* s = spins + r * N;
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t r = r_first + q;
+        uint8_t* s = spins + q * N;
         for (int64_t t = t0; t < t0 + ns; ++t) {
             for (int colour = 0; colour < 2; ++colour) {
                 for (int i = 0; i < N; ++i) {
@@ -265,12 +274,18 @@ void orc_sweep(int dim, int L, const int8_t* J, uint64_t seed, double beta,
                     else accept = orc_met_accept(seed, r, t, colour, i, T[dE + 2 * z]);
                     if (accept) {
                         s[i] ^= 1;
-                        E[r] += dE;
+                        E[q] += dE;
                     }
                 }
             }
         }
     }
+}
+
+void orc_sweep(int dim, int L, const int8_t* J, uint64_t seed, double beta,
+               int64_t R, uint8_t* spins, int32_t* E, int64_t t0, int ns)
+{
+    orc_sweep_range(dim, L, J, seed, beta, 0, R, spins, E, t0, ns);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -382,14 +397,12 @@ int64_t orc_poisson(double lambda, uint64_t seed, int64_t j, int64_t k)
 /* New population: the copies of replica j, in order of j.                     */
 /* out[0] = S, out[1] = ln Q, out[2] = E_lo.                                   */
 /* ------------------------------------------------------------------------- */
-int orc_resample(int dim, int L, uint64_t seed, int64_t k, double beta_from, double beta_to,
-                 double R_target, int64_t R, const uint8_t* spins, const int32_t* E,
-                 int64_t capacity, uint8_t* spins_new, int32_t* E_new,
-                 int32_t* counts, int64_t* offsets, double* out, int64_t* R_new)
+/* Q and the copy numbers (the first half of the step): counts[j] for j < R, and
+ * out[0] = S, out[1] = ln Q, out[2] = E_lo */
+int orc_copy_numbers(uint64_t seed, int64_t k, double beta_from, double beta_to, double R_target, int64_t R,
+                     const int32_t* E, int32_t* counts, double* out)
 {
-    int N = orc_num_sites(dim, L);
     double dbeta = beta_to - beta_from;
-    *R_new = 0;
     if (R <= 0 || !(dbeta >= 0.0) || !(R_target > 0.0)) return ORC_ERR_ARG;
 
     int32_t E_lo = E[0], E_hi = E[0];
@@ -417,11 +430,24 @@ int orc_resample(int dim, int L, uint64_t seed, int64_t k, double beta_from, dou
     out[2] = (double)E_lo;
     if (!isfinite(S) || !(S > 0.0)) return ORC_ERR_NONFINITE;
 
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < R; ++j) {
         double w = exp(-dbeta * (double)(E[j] - E_lo));
         double lam = (R_target * w) / S;
         counts[j] = (int32_t)orc_poisson(lam, seed, j, k);
     }
+    return ORC_OK;
+}
+
+int orc_resample(int dim, int L, uint64_t seed, int64_t k, double beta_from, double beta_to,
+                 double R_target, int64_t R, const uint8_t* spins, const int32_t* E,
+                 int64_t capacity, uint8_t* spins_new, int32_t* E_new,
+                 int32_t* counts, int64_t* offsets, double* out, int64_t* R_new)
+{
+    int N = orc_num_sites(dim, L);
+    *R_new = 0;
+    int st = orc_copy_numbers(seed, k, beta_from, beta_to, R_target, R, E, counts, out);
+    if (st != ORC_OK) return st;
     int64_t acc = 0;
     for (int64_t j = 0; j < R; ++j) { offsets[j] = acc; acc += counts[j]; }
     offsets[R] = acc;

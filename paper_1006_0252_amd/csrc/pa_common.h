@@ -1,0 +1,116 @@
+// Internal header of libpa: device Philox, work-buffer layout, shared constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pa.h"
+
+namespace pa {
+
+// stream tags: fourth Philox counter word of each kind of draw
+constexpr uint32_t kTagInit = 1;
+constexpr uint32_t kTagMet = 2;
+constexpr uint32_t kTagTie = 3;
+constexpr uint32_t kTagPoisson = 4;
+constexpr uint32_t kTagCoupling = 5;
+
+// Poisson ladder: levels 2^m, m in [kLadderMin, kLadderMax]; Poisson(64) blocks above 64
+constexpr int kLadderMin = -20;
+constexpr int kLadderMax = 6;
+constexpr int kLadderLevels = kLadderMax - kLadderMin + 1;
+constexpr int kLadderCap = 256;  // entries per level (the largest level, 2^6, needs < 200)
+
+// scan tile: replicas per block of the device-wide exclusive scan
+constexpr int kScanTile = 1024;
+
+struct uint4v { uint32_t x, y, z, w; };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two 32x32->64
+// products of counter words 0 and 2, Weyl key schedule between rounds.
+__host__ __device__ inline uint4v philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                           uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__host__ __device__ inline uint32_t word_of(const uint4v& v, int w)
+{
+    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+// byte offsets of the scratch arrays inside pa_run.work
+struct WorkLayout {
+    size_t hist;      // int64 [n_bins]   replicas per energy bin
+    size_t bin_q;     // int64 [n_bins]   Poisson(64) blocks of the bin's mean copy number
+    size_t bin_keep;  // uint64 [n_bins]  thinning threshold floor(rem 2^(32-m))
+    size_t bin_m;     // int32 [n_bins]   ladder level m
+    size_t scan;      // int64 [n_scan + 1] block sums of the copy-number scan
+    size_t src;       // int32 [capacity] source replica of each new replica
+    size_t qhist;     // int64 [N + 1]    overlap histogram (Hamming distance)
+    size_t misc;      // int64 [64]       small reductions (E min/max, pending ln Q)
+    size_t total;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline WorkLayout work_layout(int64_t N, int64_t n_bins, int64_t capacity)
+{
+    WorkLayout w;
+    size_t o = 0;
+    w.hist = o;     o = align256(o + 8 * (size_t)n_bins);
+    w.bin_q = o;    o = align256(o + 8 * (size_t)n_bins);
+    w.bin_keep = o; o = align256(o + 8 * (size_t)n_bins);
+    w.bin_m = o;    o = align256(o + 4 * (size_t)n_bins);
+    const int64_t n_scan = (capacity + kScanTile - 1) / kScanTile;
+    w.scan = o;     o = align256(o + 8 * (size_t)(n_scan + 1));
+    w.src = o;      o = align256(o + 4 * (size_t)capacity);
+    w.qhist = o;    o = align256(o + 8 * (size_t)(N + 1));
+    w.misc = o;     o = align256(o + 8 * 64);
+    w.total = o;
+    return w;
+}
+
+template <typename T>
+__device__ inline T* work_ptr(const pa_state* st, size_t off)
+{
+    return reinterpret_cast<T*>(st->work + off);
+}
+
+// sweep parameters passed by value
+struct SweepParams {
+    uint32_t thi[8];     // top 16 bits of T64 per class c (0x10000 = always accept)
+    uint64_t T64[8];     // full thresholds per class c
+    int64_t t0;          // first global sweep index
+    int32_t n_sweeps;
+    int32_t rpb;         // replicas (u8) or 64-replica groups (bits64) per block
+};
+
+// host launch helpers (defined in the .hip files)
+int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s);
+int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s);
+int launch_resample(const pa_run& run, const pa_step& step, hipStream_t s);
+int launch_hist(const pa_run& run, hipStream_t s);
+int launch_measure(const pa_run& run, const pa_run* partner, hipStream_t s);
+int launch_free_energy(const pa_run& run, double* out, hipStream_t s);
+int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
+                                double* out, hipStream_t s);
+int build_thresholds(double beta, int z, uint64_t* T, uint8_t* always);
+int upload_ladder(hipStream_t s);
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? PA_OK : PA_ERR_HIP; }
+
+}  // namespace pa

@@ -1,0 +1,205 @@
+// Observables and estimators: energy moments after the sweeps (Sec. II: measured after
+// resampling, no weights inside a run), overlap q between replicas of two runs and
+// Gamma = Prob(|q| < 0.2) (Sec. IV), free-energy estimator (eq. sumQ), and the device
+// version of the weighted average over runs (Sec. III, eqs. weight, omega, bestf).
+#include <math.h>
+
+#include <algorithm>
+
+#include "pa_common.h"
+
+#pragma clang fp contract(off)
+
+namespace pa {
+
+constexpr int kMiscEmin = 0, kMiscEmax = 1;
+
+// energy mean (exact integer sum), variance and skewness from the histogram, into record[k]
+__global__ void __launch_bounds__(64) k_moments(pa_state* st)
+{
+    if (st->status) return;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    const int64_t* hist = work_ptr<int64_t>(st, wl.hist);
+    const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const int E_lo = (int)misc[kMiscEmin], E_hi = (int)misc[kMiscEmax];
+    const int Eb = st->E_base;
+    const int ilo = (E_lo - Eb) >> 2, ihi = (E_hi - Eb) >> 2;
+    const int64_t R = st->R;
+    int64_t s1 = 0;
+    for (int i = ilo + threadIdx.x; i <= ihi; i += 64) s1 += hist[i] * (int64_t)(Eb + 4 * i);
+    for (int off = 32; off > 0; off >>= 1) s1 += __shfl_xor(s1, off, 64);
+    const double mean = (double)s1 / (double)R;
+    if (threadIdx.x != 0) return;
+    double m2 = 0.0, m3 = 0.0;
+    for (int i = ilo; i <= ihi; ++i) {
+        const int64_t h = hist[i];
+        if (!h) continue;
+        const double d = (double)(Eb + 4 * i) - mean;
+        m2 += (double)h * (d * d);
+        m3 += (double)h * (d * d * d);
+    }
+    m2 /= (double)R;
+    m3 /= (double)R;
+    pa_record* rec = st->record + st->k;
+    rec->E_mean = mean;
+    rec->E_var = m2;
+    rec->E_skew = m2 > 0.0 ? m3 / (m2 * sqrt(m2)) : 0.0;
+}
+
+__global__ void k_qhist_clear(pa_state* st)
+{
+    int64_t* qh = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).qhist);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= st->N; i += gridDim.x * blockDim.x) qh[i] = 0;
+}
+
+// Hamming distance of replica j of run A and replica j of run B, u8 layout
+__global__ void __launch_bounds__(256) k_overlap_u8(pa_state* a, const pa_state* __restrict__ b)
+{
+    if (a->status || b->status) return;
+    const int64_t P = min(a->R, b->R);
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= P) return;
+    const int stride = a->row_stride, N = a->N;
+    const uint8_t* x = (const uint8_t*)a->spins[a->cur] + j * stride;
+    const uint8_t* y = (const uint8_t*)b->spins[b->cur] + j * stride;
+    int d = 0;
+    for (int i = lane * 16; i < N; i += 64 * 16) {
+        const uint4 u = *(const uint4*)(x + i);
+        const uint4 v = *(const uint4*)(y + i);
+        // bytes past N are padding: zero in both rows only if never written, so mask them
+        uint32_t w[4] = {u.x ^ v.x, u.y ^ v.y, u.z ^ v.z, u.w ^ v.w};
+        const int valid = min(16, N - i);
+        for (int k = 0; k < 4; ++k) {
+            const int vb = valid - 4 * k;
+            const uint32_t m = vb >= 4 ? 0xFFFFFFFFu : (vb <= 0 ? 0u : ((1u << (8 * vb)) - 1u));
+            d += __popc(w[k] & m & 0x01010101u);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if (lane == 0) {
+        int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+        atomicAdd((unsigned long long*)&qh[d], 1ull);
+    }
+}
+
+// Hamming distance, bit-packed layout: lane = pair, loop over row words
+template <typename Wt>
+__global__ void __launch_bounds__(256) k_overlap_bits(pa_state* a, const pa_state* __restrict__ b, int n_rows)
+{
+    if (a->status || b->status) return;
+    const int64_t P = min(a->R, b->R);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    const Wt* x = (const Wt*)a->spins[a->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
+    const Wt* y = (const Wt*)b->spins[b->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
+    int d = 0;
+    for (int rho = 0; rho < n_rows; ++rho) d += __popc((uint32_t)(x[(int64_t)rho * 64] ^ y[(int64_t)rho * 64]));
+    int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+    atomicAdd((unsigned long long*)&qh[d], 1ull);
+}
+
+// q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A
+__global__ void k_overlap_stats(pa_state* a, const pa_state* __restrict__ b)
+{
+    if (a->status || b->status) return;
+    const int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+    const int N = a->N;
+    double P = 0.0, q2 = 0.0, q4 = 0.0, g = 0.0;
+    for (int d = 0; d <= N; ++d) {
+        const double c = (double)qh[d];
+        const double q = (double)(N - 2 * d) / (double)N;
+        P += c;
+        q2 += c * q * q;
+        q4 += c * q * q * q * q;
+        if (fabs(q) < 0.2) g += c;
+    }
+    pa_record* rec = a->record + a->k;
+    rec->q2 = q2 / P;
+    rec->q4 = q4 / P;
+    rec->gamma = g / P;
+    rec->n_pairs = P;
+}
+
+__global__ void k_free_energy(const pa_state* __restrict__ st, double* out) { *out = st->ln_omega + st->acc; }
+
+int launch_measure(const pa_run& run, const pa_run* partner, hipStream_t s)
+{
+    int rc = launch_hist(run, s);
+    if (rc != PA_OK) return rc;
+    hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, run.state);
+    if (partner) {
+        const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
+        hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256)), dim3(256), 0, s, run.state);
+        // the partner's population must be final before it is read: both runs on the same stream,
+        // or the partner's stream joined by the caller
+        const int64_t P = std::min(run.capacity, partner->capacity);
+        if (run.layout == PA_U8) {
+            hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, run.state,
+                               (const pa_state*)partner->state);
+        } else {
+            const int n_rows = run.dim == 1 ? (run.L + 31) / 32 : run.L * run.L;
+            const int W = run.dim == 1 ? 32 : (run.L <= 8 ? 8 : (run.L <= 16 ? 16 : 32));
+            const unsigned blocks = (unsigned)((P + 255) / 256);
+            if (W == 8) hipLaunchKernelGGL(k_overlap_bits<uint8_t>, dim3(blocks), dim3(256), 0, s, run.state,
+                                           (const pa_state*)partner->state, n_rows);
+            else if (W == 16) hipLaunchKernelGGL(k_overlap_bits<uint16_t>, dim3(blocks), dim3(256), 0, s, run.state,
+                                                 (const pa_state*)partner->state, n_rows);
+            else hipLaunchKernelGGL(k_overlap_bits<uint32_t>, dim3(blocks), dim3(256), 0, s, run.state,
+                                    (const pa_state*)partner->state, n_rows);
+        }
+        hipLaunchKernelGGL(k_overlap_stats, dim3(1), dim3(1), 0, s, run.state, (const pa_state*)partner->state);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int launch_free_energy(const pa_run& run, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_free_energy, dim3(1), dim3(1), 0, s, (const pa_state*)run.state, out);
+    return hip_status(hipGetLastError());
+}
+
+// one thread per set, same arithmetic order as the host version
+__global__ void k_weighted_average(int n_sets, int M, const double* __restrict__ x, const double* __restrict__ R,
+                                   const double* __restrict__ A, int n_obs, double* __restrict__ out)
+{
+    const int set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets) return;
+    const double* xs = x + (int64_t)set * M;
+    const double* Rs = R ? R + (int64_t)set * M : nullptr;
+    const double* As = A + (int64_t)set * M * n_obs;
+    double* o = out + (int64_t)set * (n_obs + 3);
+    double xmax = -INFINITY;
+    for (int r = 0; r < M; ++r) {
+        const double xr = xs[r] + (Rs ? log(Rs[r]) : 0.0);
+        if (xr > xmax) xmax = xr;
+    }
+    double Z = 0.0, Rsum = 0.0;
+    for (int r = 0; r < M; ++r) {
+        Z += exp(xs[r] + (Rs ? log(Rs[r]) : 0.0) - xmax);
+        Rsum += Rs ? Rs[r] : 1.0;
+    }
+    for (int k = 0; k < n_obs; ++k) o[k] = 0.0;
+    for (int r = 0; r < M; ++r) {
+        const double w = exp(xs[r] + (Rs ? log(Rs[r]) : 0.0) - xmax) / Z;
+        for (int k = 0; k < n_obs; ++k) o[k] += w * As[(int64_t)r * n_obs + k];
+    }
+    o[n_obs] = xmax + log(Z) - log(Rsum);
+    double m = 0.0;
+    for (int r = 0; r < M; ++r) m += xs[r];
+    m /= (double)M;
+    double v = 0.0;
+    for (int r = 0; r < M; ++r) v += (xs[r] - m) * (xs[r] - m);
+    o[n_obs + 1] = M > 1 ? v / (double)(M - 1) : 0.0;
+    o[n_obs + 2] = m;
+}
+
+int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
+                                double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_weighted_average, dim3((unsigned)((n_sets + 63) / 64)), dim3(64), 0, s, n_sets, M, x, R, A,
+                       n_obs, out);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace pa

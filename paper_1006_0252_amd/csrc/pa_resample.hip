@@ -1,0 +1,469 @@
+// Resampling between temperatures (Sec. II, eqs. Q and wn; Poisson copy numbers with mean
+// (R_target / R~) tau_j; the new population of R~' replicas).
+//
+// Chain of kernels on the run's stream, all sized by capacity and reading the population size
+// from the device, with no host synchronisation:
+//   hist      energy histogram h (width-4 bins from E_base), E_lo, E_hi      (integer atomics)
+//   normalise S = sum_E h(E) w(E - E_lo) in ascending E (FP64, one thread, fixed order),
+//             ln Q, and per bin the mean copy number lambda = R_target w / S split into
+//             Poisson(64) blocks q, ladder level m and thinning threshold
+//   copies    Poisson(lambda) per replica from its Philox stream (integer compares only)
+//   scan      exclusive scan of the copy numbers -> offsets, R~', capacity/extinction flags
+//   src       source replica of every new replica (binary search of the offsets)
+//   gather    copy spins and energies into the other buffer
+//   finish    swap buffers, R~ = R~', accumulate ln Q, record
+// Every kernel is a no-op once the run's sticky status is set.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "pa_common.h"
+
+#pragma clang fp contract(off)
+
+namespace pa {
+
+// Poisson(2^m) inversion tables, m = kLadderMin .. kLadderMax (host-built, uploaded once)
+__device__ uint64_t g_ladder[kLadderLevels][kLadderCap];
+
+constexpr int kMiscEmin = 0, kMiscEmax = 1, kMiscLnQ = 2;  // int64 slots of the misc area
+
+// ------------------------------------------------------------------ host tables
+// C[n] = floor(CDF_{2^m}(n) 2^32) with pmf recursion p_0 = exp(-Lambda), p_n = p_{n-1} Lambda / n;
+// the table ends at the first n >= Lambda with p_n < 2^-40, that entry forced to 2^32.
+static int ladder_host(int m, uint64_t* C, int cap)
+{
+    const double Lam = ldexp(1.0, m);
+    double p = exp(-Lam);
+    double F = 0.0;
+    const double tail = ldexp(1.0, -40);
+    int n = 0;
+    for (;;) {
+        F += p;
+        if ((double)n >= Lam && p < tail) {
+            C[n] = (uint64_t)1 << 32;
+            return n + 1;
+        }
+        const double c = floor(ldexp(F, 32));
+        C[n] = c >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)c;
+        ++n;
+        p = p * Lam / (double)n;
+        if (n >= cap - 1) {
+            C[n] = (uint64_t)1 << 32;
+            return n + 1;
+        }
+    }
+}
+
+static uint64_t g_ladder_host[kLadderLevels][kLadderCap];
+static bool g_ladder_built = false;
+static int g_ladder_device_mask = 0;  // devices that hold the table
+
+int upload_ladder(hipStream_t s)
+{
+    if (!g_ladder_built) {
+        for (int m = kLadderMin; m <= kLadderMax; ++m) {
+            uint64_t* C = g_ladder_host[m - kLadderMin];
+            const int n = ladder_host(m, C, kLadderCap);
+            for (int k = n; k < kLadderCap; ++k) C[k] = (uint64_t)1 << 32;
+        }
+        g_ladder_built = true;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PA_ERR_HIP;
+    if (dev < 31 && (g_ladder_device_mask >> dev) & 1) return PA_OK;
+    if (hipMemcpyToSymbolAsync(HIP_SYMBOL(g_ladder), g_ladder_host, sizeof(g_ladder_host), 0,
+                               hipMemcpyHostToDevice, s) != hipSuccess)
+        return PA_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return PA_ERR_HIP;
+    if (dev < 31) g_ladder_device_mask |= 1 << dev;
+    return PA_OK;
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_hist_clear(pa_state* st)
+{
+    if (st->status) return;
+    int64_t* hist = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).hist);
+    int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < st->n_bins; i += gridDim.x * blockDim.x) hist[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        misc[kMiscEmin] = INT32_MAX;
+        misc[kMiscEmax] = INT32_MIN;
+    }
+}
+
+// histogram of the current population's energies (LDS-privatised when it fits)
+__global__ void __launch_bounds__(256) k_hist(pa_state* st)
+{
+    if (st->status) return;
+    extern __shared__ uint32_t sh[];
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    int64_t* hist = work_ptr<int64_t>(st, wl.hist);
+    int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const int nb = st->n_bins;
+    const bool priv = nb <= 16384;
+    const int64_t R = st->R;
+    const int32_t* E = st->energy[st->cur];
+    const int Eb = st->E_base;
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) sh[i] = 0;
+    __syncthreads();
+    int emin = INT32_MAX, emax = INT32_MIN;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R; j += (int64_t)gridDim.x * blockDim.x) {
+        const int e = E[j];
+        const int b = (e - Eb) >> 2;
+        if (priv) atomicAdd(&sh[b], 1u);
+        else atomicAdd((unsigned long long*)&hist[b], 1ull);
+        emin = min(emin, e);
+        emax = max(emax, e);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        emin = min(emin, __shfl_xor(emin, off, 64));
+        emax = max(emax, __shfl_xor(emax, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && emin <= emax) {
+        atomicMin((long long*)&misc[kMiscEmin], (long long)emin);
+        atomicMax((long long*)&misc[kMiscEmax], (long long)emax);
+    }
+    __syncthreads();
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            if (sh[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)sh[i]);
+}
+
+struct ResampleParams {
+    double beta_from, beta_to, R_target;
+    const double* w;
+    int32_t k;
+};
+
+// smallest m in [kLadderMin, kLadderMax] with 2^m >= x (0 < x <= 64)
+__device__ inline int ladder_level(double x)
+{
+    int e;
+    const double f = frexp(x, &e);
+    const int m = (f == 0.5) ? e - 1 : e;
+    return m < kLadderMin ? kLadderMin : m;
+}
+
+// one block: S in ascending energy order, ln Q, per-bin Poisson parameters, record[k]
+__global__ void __launch_bounds__(256) k_normalise(pa_state* st, ResampleParams p)
+{
+    if (st->status) return;
+    __shared__ double prod[1024];
+    __shared__ double S_sh;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    const int64_t* hist = work_ptr<int64_t>(st, wl.hist);
+    int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    int64_t* bin_q = work_ptr<int64_t>(st, wl.bin_q);
+    uint64_t* bin_keep = work_ptr<uint64_t>(st, wl.bin_keep);
+    int32_t* bin_m = work_ptr<int32_t>(st, wl.bin_m);
+    const int E_lo = (int)misc[kMiscEmin], E_hi = (int)misc[kMiscEmax];
+    const int ilo = (E_lo - st->E_base) >> 2, ihi = (E_hi - st->E_base) >> 2;
+    const int n = ihi - ilo + 1;
+    const double dbeta = p.beta_to - p.beta_from;
+    // S = sum_i h_i w_i, i ascending; products in parallel (each rounded once), sum by one thread
+    double S = 0.0;
+    for (int base = 0; base < n; base += 1024) {
+        const int cnt = min(1024, n - base);
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) prod[t] = (double)hist[ilo + base + t] * p.w[base + t];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int t = 0; t < cnt; ++t) S = S + prod[t];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S_sh = S;
+    __syncthreads();
+    S = S_sh;
+    const double R = (double)st->R;
+    const double Rt = p.R_target > 0.0 ? p.R_target : (double)st->R0;
+    const bool bad = !isfinite(S) || !(S > 0.0);
+    if (threadIdx.x == 0) {
+        const double lnQ = -dbeta * (double)E_lo + log(S) - log(R);
+        if (bad) {
+            st->status |= PA_FLAG_NONFINITE;
+        } else {
+            pa_record* rec = st->record + p.k;
+            rec->beta = p.beta_to;
+            rec->lnQ = lnQ;
+            rec->minus_betaF = st->ln_omega + (st->acc + lnQ);
+            rec->S = S;
+            rec->E_lo = (double)E_lo;
+            *reinterpret_cast<double*>(&misc[kMiscLnQ]) = lnQ;
+            st->E_lo = E_lo;
+            st->E_hi = E_hi;
+        }
+    }
+    if (bad) return;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double lam = (Rt * p.w[t]) / S;
+        const int b = ilo + t;
+        if (!(lam > 0.0)) {
+            bin_q[b] = 0;
+            bin_m[b] = 1000;  // no draws: copy number 0
+            bin_keep[b] = 0;
+            continue;
+        }
+        int64_t q = 0;
+        double rem = lam;
+        if (lam > 64.0) {
+            q = (int64_t)ceil(lam / 64.0) - 1;
+            rem = lam - 64.0 * (double)q;
+        }
+        const int m = ladder_level(rem);
+        bin_q[b] = q;
+        bin_m[b] = m;
+        bin_keep[b] = (uint64_t)floor(ldexp(rem, 32 - m));
+    }
+}
+
+__device__ inline int64_t invert_ladder(int m, uint32_t u)
+{
+    const uint64_t* C = g_ladder[m - kLadderMin];
+    int64_t n = 0;
+    while (!((uint64_t)u < C[n])) ++n;
+    return n;
+}
+
+// copy numbers: draw d of replica j at step k is word d mod 4 of Philox(d/4, j, k, 4)
+__global__ void __launch_bounds__(256) k_copies(pa_state* st, int32_t k)
+{
+    if (st->status) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= st->R) return;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    const int64_t* bin_q = work_ptr<int64_t>(st, wl.bin_q);
+    const uint64_t* bin_keep = work_ptr<uint64_t>(st, wl.bin_keep);
+    const int32_t* bin_m = work_ptr<int32_t>(st, wl.bin_m);
+    const int b = (st->energy[st->cur][j] - st->E_base) >> 2;
+    const int m = bin_m[b];
+    int64_t n = 0;
+    if (m != 1000) {
+        const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
+        uint32_t d = 0;
+        uint4v v = {0, 0, 0, 0};
+        auto draw = [&]() -> uint32_t {
+            if ((d & 3) == 0) v = philox10(d >> 2, (uint32_t)j, (uint32_t)k, kTagPoisson, k0, k1);
+            const uint32_t u = word_of(v, d & 3);
+            ++d;
+            return u;
+        };
+        const int64_t q = bin_q[b];
+        for (int64_t blk = 0; blk < q; ++blk) n += invert_ladder(kLadderMax, draw());
+        const int64_t K = invert_ladder(m, draw());
+        const uint64_t keep = bin_keep[b];
+        for (int64_t e = 0; e < K; ++e)
+            if ((uint64_t)draw() < keep) ++n;
+    }
+    st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
+}
+
+// block sums of the copy numbers over tiles of kScanTile replicas
+__global__ void __launch_bounds__(256) k_scan_reduce(pa_state* st)
+{
+    if (st->status) return;
+    __shared__ int64_t part[4];
+    const int64_t R = st->R;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t acc = 0;
+    for (int t = threadIdx.x; t < kScanTile; t += blockDim.x)
+        if (base + t < R) acc += st->counts[base + t];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t* scan = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).scan);
+        scan[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+    }
+}
+
+// exclusive scan of the block sums (one block), total R~', capacity and extinction checks
+__global__ void __launch_bounds__(256) k_scan_top(pa_state* st, int n_blocks)
+{
+    if (st->status) return;
+    __shared__ int64_t carry_sh;
+    __shared__ int64_t wsum[4];
+    int64_t* scan = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).scan);
+    if (threadIdx.x == 0) carry_sh = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int base = 0; base < n_blocks; base += 256) {
+        const int i = base + threadIdx.x;
+        const int64_t v = i < n_blocks ? scan[i] : 0;
+        int64_t x = v;  // inclusive wave scan
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t pre = carry_sh;
+        for (int w = 0; w < wv; ++w) pre += wsum[w];
+        if (i < n_blocks) scan[i] = pre + x - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry_sh = pre + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t total = carry_sh;
+        st->R_new = total;
+        if (total > st->capacity) st->status |= PA_FLAG_CAPACITY;
+        else if (total == 0) st->status |= PA_FLAG_EXTINCT;
+    }
+}
+
+// offsets[j] = scan[tile] + exclusive scan inside the tile; offsets[R] = R~'
+__global__ void __launch_bounds__(256) k_scan_down(pa_state* st)
+{
+    if (st->status) return;
+    __shared__ int64_t wsum[4];
+    __shared__ int64_t carry_sh;
+    const int64_t R = st->R;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= R) return;
+    const int64_t* scan = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).scan);
+    if (threadIdx.x == 0) carry_sh = scan[blockIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t0 = 0; t0 < kScanTile; t0 += 256) {
+        const int64_t j = base + t0 + threadIdx.x;
+        const int64_t v = j < R ? st->counts[j] : 0;
+        int64_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t pre = carry_sh;
+        for (int w = 0; w < wv; ++w) pre += wsum[w];
+        if (j < R) st->offsets[j] = pre + x - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry_sh = pre + x;
+        __syncthreads();
+    }
+    if (base + kScanTile >= R && threadIdx.x == 0) st->offsets[R] = st->R_new;
+}
+
+// source replica of each new replica: largest j with offsets[j] <= r'
+__global__ void __launch_bounds__(256) k_src(pa_state* st)
+{
+    if (st->status) return;
+    const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rn >= st->R_new) return;
+    const int64_t* off = st->offsets;
+    int64_t lo = 0, hi = st->R;  // invariant: off[lo] <= rn < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= rn) lo = mid;
+        else hi = mid;
+    }
+    int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
+    src[rn] = (int32_t)lo;
+}
+
+// u8 gather: one thread per 16 bytes of a destination row
+__global__ void __launch_bounds__(256) k_gather_u8(pa_state* st)
+{
+    if (st->status) return;
+    const int per_row = st->row_stride / 16;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rn = t / per_row;
+    const int c = (int)(t - rn * per_row);
+    if (rn >= st->R_new) return;
+    const int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
+    const int64_t j = src[rn];
+    const int cur = st->cur;
+    const uint4* a = (const uint4*)((const uint8_t*)st->spins[cur] + j * st->row_stride) + c;
+    uint4* b = (uint4*)((uint8_t*)st->spins[cur ^ 1] + rn * st->row_stride) + c;
+    *b = *a;
+    if (c == 0) st->energy[cur ^ 1][rn] = st->energy[cur][j];
+}
+
+// bit-packed gather: lane = destination replica, loop over rows; a row word of replica j sits
+// at (j/64 * n_rows + rho) * 64 + j mod 64
+template <typename Wt>
+__global__ void __launch_bounds__(256) k_gather_bits(pa_state* st, int n_rows)
+{
+    if (st->status) return;
+    const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rn >= st->R_new) return;
+    const int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
+    const int64_t j = src[rn];
+    const int cur = st->cur;
+    const Wt* a = (const Wt*)st->spins[cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
+    Wt* b = (Wt*)st->spins[cur ^ 1] + ((rn >> 6) * n_rows) * 64 + (rn & 63);
+    for (int rho = 0; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
+    st->energy[cur ^ 1][rn] = st->energy[cur][j];
+}
+
+__global__ void k_finish(pa_state* st, ResampleParams p)
+{
+    if (st->status) return;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const double lnQ = *reinterpret_cast<const double*>(&misc[kMiscLnQ]);
+    st->acc = st->acc + lnQ;
+    st->cur ^= 1;
+    st->R = st->R_new;
+    st->k = p.k;
+    st->beta = p.beta_to;
+    st->record[p.k].R = (double)st->R_new;
+}
+
+int launch_hist(const pa_run& run, hipStream_t s)
+{
+    pa_sizes sz;
+    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.capacity, run.n_records, &sz);
+    if (rc != PA_OK) return rc;
+    const size_t hist_lds = sz.n_bins <= 16384 ? (size_t)sz.n_bins * 4 : 0;
+    const unsigned hist_blocks = (unsigned)std::min<int64_t>(1024, (run.capacity + 255) / 256);
+    hipLaunchKernelGGL(k_hist_clear, dim3(32), dim3(256), 0, s, run.state);
+    hipLaunchKernelGGL(k_hist, dim3(hist_blocks), dim3(256), hist_lds, s, run.state);
+    return PA_OK;
+}
+
+int launch_resample(const pa_run& run, const pa_step& step, hipStream_t s)
+{
+    pa_sizes sz;
+    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.capacity, run.n_records, &sz);
+    if (rc != PA_OK) return rc;
+    ResampleParams p;
+    p.beta_from = step.beta_from;
+    p.beta_to = step.beta_to;
+    p.R_target = step.R_target;
+    p.w = step.weights;
+    p.k = step.k;
+    const unsigned cap_blocks = (unsigned)((run.capacity + 255) / 256);
+    const int n_scan = (int)((run.capacity + kScanTile - 1) / kScanTile);
+    launch_hist(run, s);
+    hipLaunchKernelGGL(k_normalise, dim3(1), dim3(256), 0, s, run.state, p);
+    hipLaunchKernelGGL(k_copies, dim3(cap_blocks), dim3(256), 0, s, run.state, (int32_t)step.k);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan), dim3(256), 0, s, run.state);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, run.state, n_scan);
+    hipLaunchKernelGGL(k_scan_down, dim3(n_scan), dim3(256), 0, s, run.state);
+    hipLaunchKernelGGL(k_src, dim3(cap_blocks), dim3(256), 0, s, run.state);
+    if (run.layout == PA_U8) {
+        const int64_t threads = run.capacity * (sz.row_stride / 16);
+        hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.state);
+    } else {
+        const int n_rows = run.dim == 1 ? (run.L + 31) / 32 : run.L * run.L;
+        const int W = run.dim == 1 ? 32 : (run.L <= 8 ? 8 : (run.L <= 16 ? 16 : 32));
+        if (W == 8) hipLaunchKernelGGL(k_gather_bits<uint8_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
+        else if (W == 16) hipLaunchKernelGGL(k_gather_bits<uint16_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
+        else hipLaunchKernelGGL(k_gather_bits<uint32_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, run.state, p);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace pa
+
+extern "C" int pa_ladder_table(int m, uint64_t* C, int cap, int* len)
+{
+    if (!C || !len || cap < 2 || m < pa::kLadderMin || m > pa::kLadderMax) return PA_ERR_ARG;
+    *len = pa::ladder_host(m, C, cap);
+    return PA_OK;
+}

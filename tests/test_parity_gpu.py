@@ -1,0 +1,325 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeds.
+
+Bar: spins, energies, copy numbers, offsets and population sizes bit-exact; FP64 values
+(ln Q, -beta F, energy moments, overlap statistics) within 1e-12 relative (they differ only
+through the device's log/exp/sqrt last-bit rounding and summation order of variance sums).
+Sizes span several waves, blocks and a ragged tail of the last 64-replica group; the
+C4-shaped test runs the full 1e6-replica population and checks sampled replicas one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on a CPU machine only when -m gpu is asked for
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1006_0252_amd import pa  # noqa: E402
+
+DEV = "cuda:0"
+RTOL = 1e-12
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def close(a, b, rtol=RTOL, atol=0.0):
+    return abs(a - b) <= rtol * max(1.0, abs(b)) + atol
+
+
+def make_run(dim, L, R0, layout, seed=7, dseed=3, n_records=8, capacity=None):
+    run = pa.Run(dim, L, R0, seed, dseed, n_records=n_records, capacity=capacity, layout=layout, device=DEV)
+    run.init()
+    return run
+
+
+INIT_CASES = [
+    (1, 64, "u8", 150), (1, 64, "bits64", 150), (1, 100, "u8", 70), (1, 100, "bits64", 70),
+    (3, 2, "u8", 100), (3, 2, "bits64", 100), (3, 4, "bits64", 200), (3, 6, "u8", 130), (3, 6, "bits64", 130),
+    (3, 8, "u8", 200), (3, 8, "bits64", 200), (3, 10, "bits64", 90), (3, 12, "bits64", 70),
+    (3, 16, "u8", 70), (3, 16, "bits64", 130),
+]
+
+
+@pytest.mark.parametrize("dim,L,layout,R0", INIT_CASES)
+def test_init_parity(dim, L, layout, R0):
+    note(f"init dim={dim} L={L} {layout} R0={R0}")
+    run = make_run(dim, L, R0, layout)
+    J = run.couplings()
+    assert np.array_equal(J, o.couplings(dim, L, 3))
+    s, E = run.population()
+    so, Eo = o.init_population(dim, L, J, 7, R0)
+    assert np.array_equal(s, so) and np.array_equal(E, Eo)
+    rec = run.records()[0]
+    assert rec[2] == o.num_sites(dim, L) * math.log(2.0) or close(rec[2], o.num_sites(dim, L) * math.log(2.0))
+    info = run.query()
+    assert info.R == R0 and info.status == 0 and info.k == 0
+
+
+def test_init_with_host_couplings():
+    note("init with host couplings")
+    dim, L, R0 = 3, 6, 100
+    J = np.where(np.random.default_rng(4).random(3 * L ** 3) < 0.3, -1, 1).astype(np.int8)
+    run = pa.Run(dim, L, R0, 5, 0, n_records=2, layout="bits64", device=DEV)
+    run.init(J)
+    assert np.array_equal(run.couplings(), J)
+    s, E = run.population()
+    so, Eo = o.init_population(dim, L, J, 5, R0)
+    assert np.array_equal(s, so) and np.array_equal(E, Eo)
+
+
+SWEEP_BETAS = [0.0, 0.35, 1.2, 5.0]
+
+
+@pytest.mark.parametrize("dim,L,layout,R0", INIT_CASES)
+def test_sweep_parity(dim, L, layout, R0):
+    J = o.couplings(dim, L, 3)
+    for beta in SWEEP_BETAS:
+        note(f"sweep dim={dim} L={L} {layout} R0={R0} beta={beta}")
+        run = make_run(dim, L, R0, layout)
+        sched = pa.Schedule([0.0, beta] if beta > 0 else [0.0, 0.0], 2, run.n_bins, device=DEV)
+        step = sched.step(1)
+        step.t0 = 3
+        run.sweep(step)
+        s, E = run.population()
+        so, Eo = o.init_population(dim, L, J, 7, R0)
+        o.sweep(dim, L, J, 7, beta, R0, so, Eo, 3, 2)
+        assert np.array_equal(s, so), f"spins differ at beta={beta}"
+        assert np.array_equal(E, Eo), f"energies differ at beta={beta}"
+
+
+@pytest.mark.parametrize("L,layout", [(16, "bits64"), (10, "bits64"), (8, "u8"), (12, "u8")])
+def test_sweep_launch_shapes_agree(L, layout):
+    # every launch shape (lanes per replica, waves per block) gives the same sample
+    R0 = 200
+    J = o.couplings(3, L, 3)
+    so, Eo = o.init_population(3, L, J, 7, R0)
+    o.sweep(3, L, J, 7, 0.8, R0, so, Eo, 0, 3)
+    try:
+        for lpr, wpb in ((1, 1), (1, 4), (2, 2), (2, 4), (4, 1), (4, 3)):
+            note(f"sweep shape L={L} {layout} lpr={lpr} wpb={wpb}")
+            pa.set_sweep_config(lpr, wpb)
+            run = make_run(3, L, R0, layout)
+            sched = pa.Schedule([0.0, 0.8], 3, run.n_bins, device=DEV)
+            run.sweep(sched.step(1))
+            s, E = run.population()
+            assert np.array_equal(s, so) and np.array_equal(E, Eo), f"lpr={lpr} wpb={wpb}"
+    finally:
+        pa.set_sweep_config(0, 0)
+
+
+RESAMPLE_CASES = [(1, 64, "u8", 300), (1, 64, "bits64", 300), (3, 4, "bits64", 500), (3, 6, "u8", 400),
+                  (3, 8, "bits64", 700), (3, 10, "u8", 200), (3, 16, "bits64", 150)]
+
+
+@pytest.mark.parametrize("dim,L,layout,R0", RESAMPLE_CASES)
+def test_resample_parity(dim, L, layout, R0):
+    J = o.couplings(dim, L, 3)
+    for b0, b1 in ((0.0, 0.1), (0.6, 0.75), (2.0, 3.5)):
+        note(f"resample dim={dim} L={L} {layout} R0={R0} {b0}->{b1}")
+        run = make_run(dim, L, R0, layout, n_records=4)
+        sched = pa.Schedule([b0, b1], 2, run.n_bins, device=DEV)
+        step = sched.step(1)
+        so, Eo = o.init_population(dim, L, J, 7, R0, capacity=run.capacity)
+        if b0 > 0:
+            run.sweep(pa.Schedule([0.0, b0], 2, run.n_bins, device=DEV).step(1))
+            o.sweep(dim, L, J, 7, b0, R0, so, Eo, 0, 2)
+        run.resample(step)
+        r = o.resample(dim, L, 7, 1, b0, b1, R0, R0, so, Eo, run.capacity)
+        assert r["status"] == 0
+        info = run.query()
+        assert info.status == 0 and info.R == r["R_new"] and info.k == 1
+        c, off = run.counts_offsets(R0)
+        assert np.array_equal(c, r["counts"]) and np.array_equal(off, r["offsets"])
+        s, E = run.population()
+        assert np.array_equal(s, r["s"][: r["R_new"]]) and np.array_equal(E, r["E"][: r["R_new"]])
+        rec = run.records()[1]
+        assert rec[5] == r["E_lo"] and rec[3] == r["S"], "S must be bit-identical (fixed summation order)"
+        assert close(rec[1], r["lnQ"]) and rec[4] == r["R_new"]
+        assert close(rec[2], o.num_sites(dim, L) * math.log(2.0) + r["lnQ"])
+
+
+RUN_CASES = [
+    ("ring C1", 1, 64, "u8", 1000, 51, 5),
+    ("ring C1 bits", 1, 64, "bits64", 1000, 51, 5),
+    ("cube L8 reduced", 3, 8, "u8", 1500, 21, 10),
+    ("cube L6 bits", 3, 6, "bits64", 900, 16, 4),
+    ("cube L10 bits", 3, 10, "bits64", 400, 11, 4),
+    ("cube L16 bits reduced", 3, 16, "bits64", 260, 7, 10),
+]
+
+
+@pytest.mark.parametrize("name,dim,L,layout,R0,nT,ns", RUN_CASES)
+def test_full_run_parity(name, dim, L, layout, R0, nT, ns):
+    note(f"full run {name}")
+    betas = [5.0 * k / (nT - 1) for k in range(nT)]
+    seed, dseed = 2024, 5
+    run = pa.Run(dim, L, R0, seed, dseed, n_records=nT, layout=layout, device=DEV)
+    run.init()
+    sched = pa.Schedule(betas, ns, run.n_bins, device=DEV)
+    for k in range(1, nT):
+        st = sched.step(k)
+        run.resample(st)
+        run.sweep(st)
+        pa.measure([run])
+    J = o.couplings(dim, L, dseed)
+    st_o, rec_o, s_o, E_o = o.run(dim, L, J, seed, R0, betas, ns, capacity=run.capacity)
+    assert st_o == 0
+    code, flags = run.status()
+    assert code == pa.PA_OK and flags == 0
+    rec = run.records()
+    for k in range(nT):
+        assert rec[k, 4] == rec_o[k, 1], f"R differs at k={k}"
+        assert close(rec[k, 1], rec_o[k, 2]), f"ln Q differs at k={k}"
+        assert close(rec[k, 2], rec_o[k, 3]), f"-beta F differs at k={k}"
+        if k > 0:
+            assert rec[k, 6] == rec_o[k, 4], f"E mean differs at k={k}"
+            assert close(rec[k, 7], rec_o[k, 5], rtol=1e-12, atol=1e-12), f"E var differs at k={k}"
+            assert close(rec[k, 8], rec_o[k, 6], rtol=1e-9, atol=1e-9), f"E skew differs at k={k}"
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+    fe = torch.zeros(1, dtype=torch.float64, device=DEV)
+    run.free_energy(fe)
+    assert close(float(fe.cpu()[0]), rec_o[-1, 3])
+
+
+@pytest.mark.parametrize("dim,L,layout", [(1, 64, "u8"), (3, 8, "bits64"), (3, 6, "u8"), (3, 16, "bits64")])
+def test_overlap_parity(dim, L, layout):
+    note(f"overlap dim={dim} L={L} {layout}")
+    nT, ns = 6, 3
+    betas = [1.5 * k / (nT - 1) for k in range(nT)]
+    RA, RB = 330, 270
+    a = pa.Run(dim, L, RA, 101, 9, n_records=nT, layout=layout, device=DEV).init()
+    b = pa.Run(dim, L, RB, 202, 9, n_records=nT, layout=layout, device=DEV).init()
+    sa = pa.Schedule(betas, ns, a.n_bins, device=DEV)
+    for k in range(1, nT):
+        for run in (a, b):
+            st = sa.step(k)
+            run.resample(st)
+            run.sweep(st)
+        pa.measure([a, b], [1, 0])
+    J = o.couplings(dim, L, 9)
+    _, rec_a, s_a, _ = o.run(dim, L, J, 101, RA, betas, ns, capacity=a.capacity)
+    _, rec_b, s_b, _ = o.run(dim, L, J, 202, RB, betas, ns, capacity=b.capacity)
+    h, P = o.overlap_hist(o.num_sites(dim, L), s_a, s_b)
+    q2, q4, g = o.overlap_stats(o.num_sites(dim, L), h)
+    for run in (a, b):
+        rec = run.records()[nT - 1]
+        assert rec[12] == P
+        assert close(rec[9], q2) and close(rec[10], q4) and close(rec[11], g)
+
+
+def test_capacity_and_extinction_flags_leave_state_unchanged():
+    dim, L, R0 = 3, 6, 200
+    note("capacity overflow")
+    run = make_run(dim, L, R0, "bits64", capacity=256)
+    s0, E0 = run.population()
+    sched = pa.Schedule([0.0, 0.1], 1, run.n_bins, device=DEV, R_targets=[0, 5000.0])
+    run.resample(sched.step(1))
+    code, flags = run.status()
+    assert code == pa.PA_ERR_CAPACITY and flags & pa.PA_FLAG_CAPACITY
+    info = run.query()
+    assert info.R == R0 and info.k == 0 and info.R_new > 256
+    s1, E1 = run.population()
+    assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
+    # sticky: later calls do nothing
+    run.sweep(sched.step(1))
+    s2, _ = run.population()
+    assert np.array_equal(s0, s2)
+    note("extinction")
+    run = make_run(dim, L, R0, "u8")
+    sched = pa.Schedule([0.0, 0.1], 1, run.n_bins, device=DEV, R_targets=[0, 1e-9])
+    run.resample(sched.step(1))
+    code, flags = run.status()
+    assert code == pa.PA_ERR_EXTINCT and flags & pa.PA_FLAG_EXTINCT
+    assert run.query().R == R0
+
+
+def test_bad_step_rejected_on_host():
+    run = make_run(3, 4, 64, "u8")
+    sched = pa.Schedule([0.5, 0.2], 1, run.n_bins, device=DEV)
+    with pytest.raises(pa.PAError):
+        run.resample(sched.step(1))  # beta decreases
+
+
+def test_device_weighted_average_matches_host():
+    note("device weighted average")
+    rng = np.random.default_rng(5)
+    n_sets, M, n_obs = 3, 17, 2
+    x = rng.normal(size=(n_sets, M)) + 500
+    A = rng.normal(size=(n_sets, M, n_obs))
+    R = rng.uniform(1e4, 1e5, (n_sets, M))
+    xd = torch.tensor(x, device=DEV)
+    Ad = torch.tensor(A, device=DEV)
+    Rd = torch.tensor(R, device=DEV)
+    out = torch.zeros((n_sets, n_obs + 3), dtype=torch.float64, device=DEV)
+    pa.check(pa.lib().pa_weighted_average_dev(n_sets, M, xd.data_ptr(), Rd.data_ptr(), Ad.data_ptr(), n_obs,
+                                              out.data_ptr(), torch.cuda.current_stream().cuda_stream))
+    res = out.cpu().numpy()
+    for s_ in range(n_sets):
+        ref = o.weighted_average(x[s_], A[s_], R[s_])
+        assert np.allclose(res[s_, :n_obs], ref["A_bar"], rtol=1e-12)
+        assert close(res[s_, n_obs], ref["minus_betaF_bar"])
+        assert close(res[s_, n_obs + 1], ref["var"]) and close(res[s_, n_obs + 2], ref["mean"])
+
+
+def test_full_size_c4_sampled():
+    # the throughput configuration at its real size: L = 16, R0 = 1e6, bit-packed; the oracle
+    # checks sampled replicas one by one (a replica's sweep depends only on its own spins and
+    # index) and all 1e6 copy numbers from the energies
+    dim, L, R0 = 3, 16, 1_000_000
+    seed, dseed = 77, 1
+    note("C4 full size: init")
+    run = pa.Run(dim, L, R0, seed, dseed, n_records=4, layout="bits64", device=DEV)
+    run.init()
+    J = run.couplings()
+    assert np.array_equal(J, o.couplings(dim, L, dseed))
+    sample = np.array([0, 1, 63, 64, 65, 4097, 123457, 500000, 999935, 999936, R0 - 2, R0 - 1])
+    s = run.replica_spins(sample)
+    E = run.energies()
+    assert len(E) == R0
+    for n, r in enumerate(sample):
+        so, Eo = o.init_replicas(dim, L, J, seed, int(r), 1)
+        assert np.array_equal(s[n], so[0]) and E[r] == Eo[0]
+    note("C4 full size: sweep beta=1.0")
+    betas = [0.0, 1.0, 1.0 + 1.0 / 60.0]
+    sched = pa.Schedule(betas, 10, run.n_bins, device=DEV)
+    st = sched.step(1)
+    st.t0 = 120
+    run.sweep(st)
+    s1 = run.replica_spins(sample)
+    E1 = run.energies()
+    for n, r in enumerate(sample):
+        so = s[n : n + 1].copy()
+        Eo = E[r : r + 1].copy()
+        o.sweep_replicas(dim, L, J, seed, 1.0, int(r), so, Eo, 120, 10)
+        assert np.array_equal(s1[n], so[0]) and E1[r] == Eo[0], f"replica {r}"
+    note("C4 full size: resample 1.0 -> 1.0 + 1/60")
+    old_buf = run.query().cur
+    st2 = sched.step(2)
+    run.resample(st2)
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    stc, counts_o, S_o, lnQ_o, Elo_o = o.copy_numbers(seed, 2, betas[1], betas[2], R0, E1)
+    assert stc == 0
+    c, off = run.counts_offsets(R0)
+    assert np.array_equal(c, counts_o)
+    assert off[0] == 0 and np.array_equal(np.diff(off), c)
+    rec = run.records()[2]
+    assert rec[3] == S_o and close(rec[1], lnQ_o) and rec[5] == Elo_o
+    E2 = run.energies()
+    assert len(E2) == off[-1]
+    src = np.searchsorted(off, np.arange(len(E2)), side="right") - 1
+    assert np.array_equal(E2, E1[src])
+    pick = np.unique(np.concatenate([np.arange(0, len(E2), 99991), [len(E2) - 1]]))
+    new_s = run.replica_spins(pick)
+    old_s = run.replica_spins(src[pick], buf=old_buf)
+    assert np.array_equal(new_s, old_s)
