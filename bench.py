@@ -1,0 +1,175 @@
+"""Throughput benchmark: population annealing at L = 16 on one MI355X.
+
+Workload (the throughput configuration): 3D +-J spin glass, L = 16 (4096 spins),
+R0 = 1e6 replicas bit-packed (0.5 GB per population buffer), beta linear 0 -> 5 in 301
+temperatures, 10 Metropolis sweeps per temperature.  Couplings and initial spins are drawn
+from seeds on the device (synthetic data).
+
+A step is one temperature of the schedule through the whole hot path: resample
+(histogram, FP64 normalisation, Poisson copy numbers, scan, gather), 10 fused sweeps,
+measurement (energy moments) and the free-energy estimate.  W warm-up steps run first
+(untimed), then K steps are timed between device synchronisations; the population is
+resident in HBM throughout.  value = spin-flip attempts (replicas x spins x sweeps) per
+second over the K timed steps.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel (the sweep,
+timed live with HIP events on its stream) and the CPU oracle's throughput on a bounded
+sample of the same sweep (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-flip attempts/s at L=16; wall time to var(βF)≤1e-3, learned vs fixed Δβ"
+# algorithmic VALU work per Metropolis attempt, int32 lane-ops: 1/8 of a Philox4x32-10 call
+# (10 rounds x (2 wide multiplies + 2 three-input xors) = 40 ops per call, 8 attempts per call)
+# plus the threshold select, compare and flip (3 ops)
+OPS_PER_ATTEMPT = 40 / 8 + 3
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-ops per second
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=295)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--L", type=int, default=16)
+    p.add_argument("--R0", type=int, default=1_000_000)
+    p.add_argument("--n-temps", type=int, default=301)
+    p.add_argument("--n-sweeps", type=int, default=10)
+    p.add_argument("--layout", default="bits64")
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
+    return p.parse_args()
+
+
+def cpu_baseline(L, R0, n_sweeps, target_s):
+    """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
+    from oracle import oracle as o
+
+    dim = 3
+    J = o.couplings(dim, L, 1)
+    threads = o.num_threads()
+    n = max(threads, 16)
+    s, E = o.init_replicas(dim, L, J, 1, 0, n)
+    t = time.perf_counter()
+    o.sweep_replicas(dim, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
+    dt = time.perf_counter() - t
+    per_rep = dt / n
+    m = int(min(R0, max(threads, target_s / max(per_rep, 1e-9))))
+    s, E = o.init_replicas(dim, L, J, 1, 0, m)
+    t = time.perf_counter()
+    o.sweep_replicas(dim, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
+    dt = time.perf_counter() - t
+    attempts = m * L ** 3 * n_sweeps
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle sweep of the first {m} replicas of the L={L} population, {n_sweeps} sweeps at "
+                      f"beta=1 ({attempts:.3e} attempts in {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing to do", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1006_0252_amd import pa
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = "cuda:0"
+    n_steps = args.n_temps - 1
+    if args.warmup + args.steps > n_steps:
+        print(f"warmup + steps must not exceed the {n_steps} steps of the schedule", file=sys.stderr)
+        sys.exit(2)
+    betas = pa.linear_schedule(args.n_temps, 5.0)
+    cap = int(np.ceil(args.R0 * 1.25 / 64)) * 64
+    run = pa.Run(3, args.L, args.R0, seed=1, disorder_seed=1, n_records=args.n_temps, capacity=cap,
+                 layout=args.layout, device=dev)
+    run.init()
+    sched = pa.Schedule(betas, args.n_sweeps, run.n_bins, device=dev)
+    fe = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    N = run.N
+
+    def step(k, ev=None):
+        st = sched.step(k)
+        run.resample(st)
+        if ev is not None:
+            ev[0].record(stream)
+        run.sweep(st)
+        if ev is not None:
+            ev[1].record(stream)
+        pa.measure([run])
+        run.free_energy(fe)
+
+    for k in range(1, args.warmup + 1):
+        step(k)
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ks = list(range(args.warmup + 1, args.warmup + args.steps + 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, k in enumerate(ks):
+        step(k, events[i])
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    code, flags = run.status()
+    if code != pa.PA_OK:
+        raise RuntimeError(f"run failed: status {code} flags {flags}")
+    rec = run.records()
+    R_steps = rec[ks, 4]
+    attempts = float(np.sum(R_steps) * N * args.n_sweeps)
+    value = attempts / T
+    sweep_ms = np.array([a.elapsed_time(b) for a, b in events])
+    sweep_s = float(np.mean(sweep_ms)) * 1e-3
+    per_launch_attempts = float(np.mean(R_steps)) * N * args.n_sweeps
+    achieved = per_launch_attempts * OPS_PER_ATTEMPT / sweep_s
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            traffic = tr.get("bytes_per_launch")
+        except (ValueError, OSError):
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"cube_L{args.L}_R{args.R0}_{args.layout}", "L": args.L, "R0": args.R0,
+                   "n_temps": args.n_temps, "n_sweeps": args.n_sweeps, "layout": args.layout,
+                   "steps_timed": f"k={ks[0]}..{ks[-1]}", "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                     "kernel": "k_sweep3 (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
+                     "ops_per_attempt": OPS_PER_ATTEMPT},
+        "sweep_attempts_per_s": per_launch_attempts / sweep_s,
+        "final_minus_betaF": float(rec[ks[-1], 2]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.L, args.R0, args.n_sweeps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

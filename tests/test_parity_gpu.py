@@ -245,9 +245,19 @@ def test_capacity_and_extinction_flags_leave_state_unchanged():
 
 def test_bad_step_rejected_on_host():
     run = make_run(3, 4, 64, "u8")
-    sched = pa.Schedule([0.5, 0.2], 1, run.n_bins, device=DEV)
     with pytest.raises(pa.PAError):
-        run.resample(sched.step(1))  # beta decreases
+        pa.Schedule([0.5, 0.2], 1, run.n_bins, device=DEV)  # no weight table for a negative step
+    sched = pa.Schedule([0.2, 0.5], 1, run.n_bins, device=DEV)
+    st = sched.step(1)
+    st.beta_from, st.beta_to = 0.5, 0.2  # beta decreases
+    with pytest.raises(pa.PAError) as e:
+        run.resample(st)
+    assert e.value.code == pa.PA_ERR_ARG
+    st = sched.step(1)
+    st.k = 0
+    with pytest.raises(pa.PAError):
+        run.resample(st)
+    assert run.query().k == 0 and run.status()[0] == pa.PA_OK
 
 
 def test_device_weighted_average_matches_host():
