@@ -161,7 +161,7 @@ def main():
                    "steps_timed": f"k={ks[0]}..{ks[-1]}", "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                     "kernel": "k_sweep3 (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
+                     "kernel": "k_sweep3f (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
                      "ops_per_attempt": OPS_PER_ATTEMPT},
         "sweep_attempts_per_s": per_launch_attempts / sweep_s,
         "final_minus_betaF": float(rec[ks[-1], 2]),

@@ -27,16 +27,16 @@ constexpr int kScanTile = 1024;
 struct uint4v { uint32_t x, y, z, w; };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two 32x32->64
-// products of counter words 0 and 2, Weyl key schedule between rounds.
-__host__ __device__ inline uint4v philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                           uint32_t k1)
+// products of counter words 0 and 2, Weyl key schedule between rounds.  The three-way xor
+// of each round is one v_bitop3 (truth table 0x96 = a ^ b ^ c) on gfx950.
+__device__ inline uint4v philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -102,6 +102,7 @@ struct SweepParams {
 // host launch helpers (defined in the .hip files)
 int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s);
 int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s);
+int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s);
 int launch_resample(const pa_run& run, const pa_step& step, hipStream_t s);
 int launch_hist(const pa_run& run, hipStream_t s);
 int launch_measure(const pa_run& run, const pa_run* partner, hipStream_t s);

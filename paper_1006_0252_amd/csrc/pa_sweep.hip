@@ -12,41 +12,12 @@
 #include <string.h>
 
 #include "pa_common.h"
+#include "pa_sweep_util.h"
 
 namespace pa {
 
 constexpr int kLayoutU8 = PA_U8;
 constexpr int kLayoutBits = PA_BITS64;
-
-// ---------------------------------------------------------------- small helpers
-// LDS writes of one wave made visible to its other lanes (each wave owns its LDS rows, so no
-// block barrier is needed once the block-shared tables are built)
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t field16(const uint4v& v, int f)
-{
-    const uint32_t w = (f >> 1) == 0 ? v.x : ((f >> 1) == 1 ? v.y : ((f >> 1) == 2 ? v.z : v.w));
-    return (f & 1) ? (w >> 16) : (w & 0xFFFFu);
-}
-
-// full 64-bit acceptance test on a first-look tie: U = (u16 << 48) | u48 < T64
-__device__ __noinline__ bool tie_accept(uint32_t u16, uint64_t T64, uint32_t site, uint32_t r, uint32_t ctr2,
-                                        uint32_t k0, uint32_t k1)
-{
-    const uint4v v = philox10(site, r, ctr2, kTagTie, k0, k1);
-    const uint64_t U = ((uint64_t)u16 << 48) | (uint64_t)v.x | ((uint64_t)(v.y & 0xFFFFu) << 32);
-    return U < T64;
-}
-
-// pack 4 bytes of 0/1 into 4 bits (byte k -> bit k)
-__device__ __forceinline__ uint32_t pack4(uint32_t d) { return ((d & 0x01010101u) * 0x01020408u) >> 24; }
-// unpack 4 bits into 4 bytes of 0/1
-__device__ __forceinline__ uint32_t unpack4(uint32_t b) { return ((b & 0xFu) * 0x00204081u) & 0x01010101u; }
 
 // ---------------------------------------------------------------- geometry
 template <int DIM, int L>
@@ -512,6 +483,14 @@ static SweepConfig default_config(int dim, int L)
     return {1, 4};
 }
 
+// launch shape of the fast cube kernel (L = 4, 8, 12, 16)
+static SweepConfig fast_config(int L)
+{
+    if (L >= 12) return {4, 4};
+    if (L >= 8) return {2, 4};
+    return {1, 4};
+}
+
 static SweepConfig g_override = {0, 0};
 
 int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
@@ -533,6 +512,12 @@ int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
     SweepConfig cfg = default_config(run.dim, run.L);
     if (g_override.lpr) cfg = g_override;
     int st;
+    if (run.dim == 3 && run.L % 4 == 0 && run.L <= 16) {
+        SweepConfig fc = g_override.lpr ? g_override : fast_config(run.L);
+        st = launch_sweep_fast(run, p, fc.lpr, fc.wpb, s);
+        if (st != PA_OK) return st;
+        return hip_status(hipGetLastError());
+    }
     if (run.dim == 1) {
         const int NR = (run.L + 31) / 32;
         if (cfg.lpr > NR) cfg.lpr = 1;
