@@ -24,7 +24,13 @@
  *     the device (capacity overflow, extinction, non-finite weights) set sticky bits in
  *     the run's device state; pa_status() reads them.  A step that raises one leaves
  *     the population unchanged.
- *   - Calls with n_runs > 1 apply the same step to every run (batching).
+ *   - Calls with n_runs > 1 apply the same step to every run (batching).  When the runs'
+ *     pa_state blocks are consecutive in device memory (state of run r at runs[0].state + r),
+ *     share one stream and one layout, each kernel is launched once for all of them: the
+ *     resampling and measurement kernels index runs by grid row, and the cube sweep (even L
+ *     from 4 to 16) is one persistent launch whose waves take (run, tile of replicas) items
+ *     from a device work list.  Otherwise the runs are processed one after the other.  The
+ *     results are the same either way (every draw is keyed by run seed and replica index).
  *
  * Physics conventions
  *   - dim 1: periodic chain of N = L spins; bond b = i joins sites i and i+1 (mod N).
@@ -116,7 +122,9 @@ typedef struct pa_state {
     double acc;     /* sum of ln Q so far */
     double ln_omega;/* N ln 2 */
     double beta;    /* current inverse temperature */
-    uint8_t pad[48];
+    uint32_t work_counter; /* work items taken by a batched sweep (used in the batch's first run) */
+    uint32_t reserved0;
+    uint8_t pad[40];
 } pa_state;
 
 /* Host descriptor of one run; every pointer but stream is a device pointer. */
@@ -254,6 +262,21 @@ int pa_thresholds(double beta, int z, uint64_t* T, uint8_t* always);
 /* Inversion table of Poisson(2^m), m in [-20, 6]: C[n] = floor(CDF(n) 2^32), last entry
  * 2^32; returns the length through *len (at most cap entries written). */
 int pa_ladder_table(int m, uint64_t* C, int cap, int* len);
+
+/* HIP graph of a whole schedule: every pa_sweep / pa_resample / pa_measure / pa_free_energy
+ * call between pa_graph_begin and pa_graph_end on `stream` (a non-null hipStream_t that all
+ * the captured runs use) is recorded instead of run; pa_graph_launch replays it on a stream.
+ * Population sizes and status live on the device, so a replay is the same computation as the
+ * eager calls.  The graph object is host-owned by the library until pa_graph_destroy. */
+int pa_graph_begin(void* stream);
+int pa_graph_end(void* stream, void** graph_exec);
+int pa_graph_launch(void* graph_exec, void* stream);
+int pa_graph_destroy(void* graph_exec);
+
+/* Persistent batched sweep schedule, for the autotuner: blocks per compute unit (1..32) and
+ * work order (0: runs as given, 1: larger lattices first); (0, 0) restores the defaults.
+ * Results do not depend on it. */
+int pa_set_batch_config(int blocks_per_cu, int order);
 
 /* Launch shape of the sweep kernels for later calls in this process: lanes per replica
  * (1, 2 or 4; a replica's rows are split among that many lanes) and waves per block (1..4).

@@ -33,6 +33,18 @@ static int check_run(const pa_run& r)
     return PA_OK;
 }
 
+// one launch per kernel for all runs: consecutive device states, one stream, one layout
+static bool batchable(const pa_run* runs, int n)
+{
+    if (n < 2) return false;
+    for (int r = 1; r < n; ++r) {
+        if (runs[r].state != runs[0].state + r) return false;
+        if (runs[r].stream != runs[0].stream || runs[r].layout != runs[0].layout || runs[r].dim != runs[0].dim)
+            return false;
+    }
+    return true;
+}
+
 static int check_step(const pa_step* s, bool need_weights)
 {
     if (!s) return PA_ERR_ARG;
@@ -123,6 +135,15 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step)
         if (st != PA_OK) return st;
     }
     if (step->n_sweeps == 0) return PA_OK;
+    bool fast = batchable(runs, n_runs) && runs[0].dim == 3 && n_runs <= 1024;
+    for (int r = 0; fast && r < n_runs; ++r) fast = fast_sweep_supported(runs[r].dim, runs[r].L);
+    if (fast) {
+        SweepParams p;
+        build_sweep_params(*step, 6, &p);
+        st = launch_sweep_batch(runs, n_runs, p, (hipStream_t)runs[0].stream);
+        if (st != PA_OK) return st;
+        return hip_status(hipGetLastError());
+    }
     for (int r = 0; r < n_runs; ++r) {
         st = launch_sweep(runs[r], *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
@@ -142,8 +163,9 @@ int pa_resample(pa_run* runs, int n_runs, const pa_step* step)
         pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].capacity, runs[r].n_records, &sz);
         if (step->n_weights < sz.n_bins || step->k >= runs[r].n_records) return PA_ERR_ARG;
     }
+    if (batchable(runs, n_runs)) return launch_resample(runs, n_runs, *step, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {
-        st = launch_resample(runs[r], *step, (hipStream_t)runs[r].stream);
+        st = launch_resample(&runs[r], 1, *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -161,9 +183,19 @@ int pa_measure(pa_run* runs, int n_runs, const int32_t* partner)
             if (p.dim != runs[r].dim || p.L != runs[r].L || p.layout != runs[r].layout) return PA_ERR_ARG;
         }
     }
+    if (batchable(runs, n_runs)) {
+        // partners either absent or the pairs (0,1), (2,3), ...: one launch per kernel
+        bool none = partner == nullptr, pairs = partner != nullptr && n_runs % 2 == 0;
+        for (int r = 0; partner && r < n_runs; ++r) {
+            if (partner[r] >= 0) none = false;
+            if (partner[r] != (r ^ 1)) pairs = false;
+        }
+        if (none) return launch_measure(runs, n_runs, nullptr, 0, (hipStream_t)runs[0].stream);
+        if (pairs) return launch_measure(runs, n_runs, nullptr, 1, (hipStream_t)runs[0].stream);
+    }
     for (int r = 0; r < n_runs; ++r) {
         const pa_run* p = (partner && partner[r] >= 0) ? &runs[partner[r]] : nullptr;
-        int st = launch_measure(runs[r], p, (hipStream_t)runs[r].stream);
+        int st = launch_measure(&runs[r], 1, p, 0, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -176,8 +208,9 @@ int pa_free_energy(const pa_run* runs, int n_runs, double* minus_betaF_dev)
         int st = check_run(runs[r]);
         if (st != PA_OK) return st;
     }
+    if (batchable(runs, n_runs)) return launch_free_energy(runs, n_runs, minus_betaF_dev, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {
-        int st = launch_free_energy(runs[r], minus_betaF_dev + r, (hipStream_t)runs[r].stream);
+        int st = launch_free_energy(&runs[r], 1, minus_betaF_dev + r, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -274,6 +307,37 @@ const char* pa_strerror(int code)
         case PA_ERR_NOT_INIT: return "run not initialised";
         default: return "unknown status";
     }
+}
+
+int pa_graph_begin(void* stream)
+{
+    if (!stream) return PA_ERR_ARG;  // capture needs a stream of its own, not the null stream
+    return hip_status(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+}
+
+int pa_graph_end(void* stream, void** graph_exec)
+{
+    if (!stream || !graph_exec) return PA_ERR_ARG;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture((hipStream_t)stream, &g) != hipSuccess || !g) return PA_ERR_HIP;
+    hipGraphExec_t e = nullptr;
+    const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (err != hipSuccess) return PA_ERR_HIP;
+    *graph_exec = (void*)e;
+    return PA_OK;
+}
+
+int pa_graph_launch(void* graph_exec, void* stream)
+{
+    if (!graph_exec) return PA_ERR_ARG;
+    return hip_status(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream));
+}
+
+int pa_graph_destroy(void* graph_exec)
+{
+    if (!graph_exec) return PA_ERR_ARG;
+    return hip_status(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
 }
 
 int pa_fill_weights(double dbeta, int64_t n, double* w)

@@ -62,6 +62,7 @@ struct WorkLayout {
     size_t src;       // int32 [capacity] source replica of each new replica
     size_t qhist;     // int64 [N + 1]    overlap histogram (Hamming distance)
     size_t misc;      // int64 [64]       small reductions (E min/max, pending ln Q)
+    size_t batch;     // int64 [1025]     work-list offsets of a batched sweep (first run of a batch)
     size_t total;
 };
 
@@ -80,6 +81,7 @@ __host__ __device__ inline WorkLayout work_layout(int64_t N, int64_t n_bins, int
     w.src = o;      o = align256(o + 4 * (size_t)capacity);
     w.qhist = o;    o = align256(o + 8 * (size_t)(N + 1));
     w.misc = o;     o = align256(o + 8 * 64);
+    w.batch = o;    o = align256(o + 8 * 1025);
     w.total = o;
     return w;
 }
@@ -103,10 +105,14 @@ struct SweepParams {
 int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s);
 int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s);
 int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s);
-int launch_resample(const pa_run& run, const pa_step& step, hipStream_t s);
-int launch_hist(const pa_run& run, hipStream_t s);
-int launch_measure(const pa_run& run, const pa_run* partner, hipStream_t s);
-int launch_free_energy(const pa_run& run, double* out, hipStream_t s);
+// batched launchers: n runs whose device states are contiguous (runs[r].state == runs[0].state + r)
+int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
+int launch_hist(const pa_run* runs, int n, hipStream_t s);
+int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xor, hipStream_t s);
+int launch_free_energy(const pa_run* runs, int n, double* out, hipStream_t s);
+int launch_sweep_batch(const pa_run* runs, int n, const SweepParams& p, hipStream_t s);
+bool fast_sweep_supported(int dim, int L);
+int build_sweep_params(const pa_step& step, int z, SweepParams* p);
 int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
                                 double* out, hipStream_t s);
 int build_thresholds(double beta, int z, uint64_t* T, uint8_t* always);

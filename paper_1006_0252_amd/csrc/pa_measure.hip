@@ -15,8 +15,9 @@ namespace pa {
 constexpr int kMiscEmin = 0, kMiscEmax = 1;
 
 // energy mean (exact integer sum), variance and skewness from the histogram, into record[k]
-__global__ void __launch_bounds__(64) k_moments(pa_state* st)
+__global__ void __launch_bounds__(64) k_moments(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     const int64_t* hist = work_ptr<int64_t>(st, wl.hist);
@@ -46,15 +47,18 @@ __global__ void __launch_bounds__(64) k_moments(pa_state* st)
     rec->E_skew = m2 > 0.0 ? m3 / (m2 * sqrt(m2)) : 0.0;
 }
 
-__global__ void k_qhist_clear(pa_state* st)
+__global__ void k_qhist_clear(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     int64_t* qh = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).qhist);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= st->N; i += gridDim.x * blockDim.x) qh[i] = 0;
 }
 
 // Hamming distance of replica j of run A and replica j of run B, u8 layout
-__global__ void __launch_bounds__(256) k_overlap_u8(pa_state* a, const pa_state* __restrict__ b)
+__global__ void __launch_bounds__(256) k_overlap_u8(pa_state* base, const pa_state* b_given, int pair_xor)
 {
+    pa_state* a = base + blockIdx.y;
+    const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
     const int64_t P = min(a->R, b->R);
     const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -85,23 +89,38 @@ __global__ void __launch_bounds__(256) k_overlap_u8(pa_state* a, const pa_state*
 
 // Hamming distance, bit-packed layout: lane = pair, loop over row words
 template <typename Wt>
-__global__ void __launch_bounds__(256) k_overlap_bits(pa_state* a, const pa_state* __restrict__ b, int n_rows)
+__device__ inline int hamming_rows(const pa_state* a, const pa_state* b, int64_t j, int n_rows)
 {
-    if (a->status || b->status) return;
-    const int64_t P = min(a->R, b->R);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P) return;
     const Wt* x = (const Wt*)a->spins[a->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
     const Wt* y = (const Wt*)b->spins[b->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
     int d = 0;
     for (int rho = 0; rho < n_rows; ++rho) d += __popc((uint32_t)(x[(int64_t)rho * 64] ^ y[(int64_t)rho * 64]));
+    return d;
+}
+
+__global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_state* b_given, int pair_xor)
+{
+    pa_state* a = base + blockIdx.y;
+    const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
+    if (a->status || b->status) return;
+    const int64_t P = min(a->R, b->R);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    const int n_rows = a->dim == 1 ? (a->N + 31) / 32 : a->L * a->L;
+    const int WB = a->dim == 1 ? 4 : (a->L <= 8 ? 1 : (a->L <= 16 ? 2 : 4));
+    int d;
+    if (WB == 1) d = hamming_rows<uint8_t>(a, b, j, n_rows);
+    else if (WB == 2) d = hamming_rows<uint16_t>(a, b, j, n_rows);
+    else d = hamming_rows<uint32_t>(a, b, j, n_rows);
     int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
     atomicAdd((unsigned long long*)&qh[d], 1ull);
 }
 
 // q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A
-__global__ void k_overlap_stats(pa_state* a, const pa_state* __restrict__ b)
+__global__ void k_overlap_stats(pa_state* base, const pa_state* b_given, int pair_xor)
 {
+    pa_state* a = base + blockIdx.y;
+    const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
     const int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
     const int N = a->N;
@@ -121,41 +140,44 @@ __global__ void k_overlap_stats(pa_state* a, const pa_state* __restrict__ b)
     rec->n_pairs = P;
 }
 
-__global__ void k_free_energy(const pa_state* __restrict__ st, double* out) { *out = st->ln_omega + st->acc; }
-
-int launch_measure(const pa_run& run, const pa_run* partner, hipStream_t s)
+__global__ void k_free_energy(const pa_state* __restrict__ base, int n, double* out)
 {
-    int rc = launch_hist(run, s);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) out[r] = base[r].ln_omega + base[r].acc;
+}
+
+// n runs with contiguous states (grid.y = run); partner: NULL, or the partner of a single run
+// (n = 1), or pair_xor: run r paired with run r ^ 1 of the same call
+int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xor, hipStream_t s)
+{
+    int rc = launch_hist(runs, n, s);
     if (rc != PA_OK) return rc;
-    hipLaunchKernelGGL(k_moments, dim3(1), dim3(64), 0, s, run.state);
-    if (partner) {
-        const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
-        hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256)), dim3(256), 0, s, run.state);
+    pa_state* base = runs[0].state;
+    hipLaunchKernelGGL(k_moments, dim3(1, n), dim3(64), 0, s, base);
+    if (partner || pair_xor) {
+        int64_t N = 0, P = 0;
+        for (int r = 0; r < n; ++r) {
+            N = std::max<int64_t>(N, runs[r].dim == 1 ? runs[r].L : (int64_t)runs[r].L * runs[r].L * runs[r].L);
+            P = std::max<int64_t>(P, runs[r].capacity);
+        }
+        const pa_state* bg = partner ? partner->state : nullptr;
+        hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), n), dim3(256), 0, s, base);
         // the partner's population must be final before it is read: both runs on the same stream,
         // or the partner's stream joined by the caller
-        const int64_t P = std::min(run.capacity, partner->capacity);
-        if (run.layout == PA_U8) {
-            hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, run.state,
-                               (const pa_state*)partner->state);
-        } else {
-            const int n_rows = run.dim == 1 ? (run.L + 31) / 32 : run.L * run.L;
-            const int W = run.dim == 1 ? 32 : (run.L <= 8 ? 8 : (run.L <= 16 ? 16 : 32));
-            const unsigned blocks = (unsigned)((P + 255) / 256);
-            if (W == 8) hipLaunchKernelGGL(k_overlap_bits<uint8_t>, dim3(blocks), dim3(256), 0, s, run.state,
-                                           (const pa_state*)partner->state, n_rows);
-            else if (W == 16) hipLaunchKernelGGL(k_overlap_bits<uint16_t>, dim3(blocks), dim3(256), 0, s, run.state,
-                                                 (const pa_state*)partner->state, n_rows);
-            else hipLaunchKernelGGL(k_overlap_bits<uint32_t>, dim3(blocks), dim3(256), 0, s, run.state,
-                                    (const pa_state*)partner->state, n_rows);
-        }
-        hipLaunchKernelGGL(k_overlap_stats, dim3(1), dim3(1), 0, s, run.state, (const pa_state*)partner->state);
+        if (runs[0].layout == PA_U8)
+            hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
+        else
+            hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + 255) / 256), n), dim3(256), 0, s, base, bg,
+                               pair_xor);
+        hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(1), 0, s, base, bg, pair_xor);
     }
     return hip_status(hipGetLastError());
 }
 
-int launch_free_energy(const pa_run& run, double* out, hipStream_t s)
+int launch_free_energy(const pa_run* runs, int n, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_free_energy, dim3(1), dim3(1), 0, s, (const pa_state*)run.state, out);
+    hipLaunchKernelGGL(k_free_energy, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, (const pa_state*)runs[0].state,
+                       n, out);
     return hip_status(hipGetLastError());
 }
 

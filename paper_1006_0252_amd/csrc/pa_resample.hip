@@ -82,8 +82,9 @@ int upload_ladder(hipStream_t s)
 }
 
 // ------------------------------------------------------------------ kernels
-__global__ void k_hist_clear(pa_state* st)
+__global__ void k_hist_clear(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     int64_t* hist = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).hist);
     int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
@@ -95,8 +96,9 @@ __global__ void k_hist_clear(pa_state* st)
 }
 
 // histogram of the current population's energies (LDS-privatised when it fits)
-__global__ void __launch_bounds__(256) k_hist(pa_state* st)
+__global__ void __launch_bounds__(256) k_hist(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     extern __shared__ uint32_t sh[];
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
@@ -149,8 +151,9 @@ __device__ inline int ladder_level(double x)
 }
 
 // one block: S in ascending energy order, ln Q, per-bin Poisson parameters, record[k]
-__global__ void __launch_bounds__(256) k_normalise(pa_state* st, ResampleParams p)
+__global__ void __launch_bounds__(256) k_normalise(pa_state* base, ResampleParams p)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     __shared__ double prod[1024];
     __shared__ double S_sh;
@@ -166,9 +169,9 @@ __global__ void __launch_bounds__(256) k_normalise(pa_state* st, ResampleParams 
     const double dbeta = p.beta_to - p.beta_from;
     // S = sum_i h_i w_i, i ascending; products in parallel (each rounded once), sum by one thread
     double S = 0.0;
-    for (int base = 0; base < n; base += 1024) {
-        const int cnt = min(1024, n - base);
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) prod[t] = (double)hist[ilo + base + t] * p.w[base + t];
+    for (int b0 = 0; b0 < n; b0 += 1024) {
+        const int cnt = min(1024, n - b0);
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) prod[t] = (double)hist[ilo + b0 + t] * p.w[b0 + t];
         __syncthreads();
         if (threadIdx.x == 0)
             for (int t = 0; t < cnt; ++t) S = S + prod[t];
@@ -228,8 +231,9 @@ __device__ inline int64_t invert_ladder(int m, uint32_t u)
 }
 
 // copy numbers: draw d of replica j at step k is word d mod 4 of Philox(d/4, j, k, 4)
-__global__ void __launch_bounds__(256) k_copies(pa_state* st, int32_t k)
+__global__ void __launch_bounds__(256) k_copies(pa_state* base, int32_t k)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= st->R) return;
@@ -261,15 +265,17 @@ __global__ void __launch_bounds__(256) k_copies(pa_state* st, int32_t k)
 }
 
 // block sums of the copy numbers over tiles of kScanTile replicas
-__global__ void __launch_bounds__(256) k_scan_reduce(pa_state* st)
+__global__ void __launch_bounds__(256) k_scan_reduce(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
+    if ((int64_t)blockIdx.x * kScanTile >= st->capacity) return;  // grid sized for the largest run
     __shared__ int64_t part[4];
     const int64_t R = st->R;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t tile0 = (int64_t)blockIdx.x * kScanTile;
     int64_t acc = 0;
     for (int t = threadIdx.x; t < kScanTile; t += blockDim.x)
-        if (base + t < R) acc += st->counts[base + t];
+        if (tile0 + t < R) acc += st->counts[tile0 + t];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -280,8 +286,10 @@ __global__ void __launch_bounds__(256) k_scan_reduce(pa_state* st)
 }
 
 // exclusive scan of the block sums (one block), total R~', capacity and extinction checks
-__global__ void __launch_bounds__(256) k_scan_top(pa_state* st, int n_blocks)
+__global__ void __launch_bounds__(256) k_scan_top(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
+    const int n_blocks = (int)((st->capacity + kScanTile - 1) / kScanTile);
     if (st->status) return;
     __shared__ int64_t carry_sh;
     __shared__ int64_t wsum[4];
@@ -289,8 +297,8 @@ __global__ void __launch_bounds__(256) k_scan_top(pa_state* st, int n_blocks)
     if (threadIdx.x == 0) carry_sh = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int base = 0; base < n_blocks; base += 256) {
-        const int i = base + threadIdx.x;
+    for (int i0 = 0; i0 < n_blocks; i0 += 256) {
+        const int i = i0 + threadIdx.x;
         const int64_t v = i < n_blocks ? scan[i] : 0;
         int64_t x = v;  // inclusive wave scan
         for (int off = 1; off < 64; off <<= 1) {
@@ -315,20 +323,21 @@ __global__ void __launch_bounds__(256) k_scan_top(pa_state* st, int n_blocks)
 }
 
 // offsets[j] = scan[tile] + exclusive scan inside the tile; offsets[R] = R~'
-__global__ void __launch_bounds__(256) k_scan_down(pa_state* st)
+__global__ void __launch_bounds__(256) k_scan_down(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     __shared__ int64_t wsum[4];
     __shared__ int64_t carry_sh;
     const int64_t R = st->R;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    if (base >= R) return;
+    const int64_t tile0 = (int64_t)blockIdx.x * kScanTile;
+    if (tile0 >= R) return;
     const int64_t* scan = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).scan);
     if (threadIdx.x == 0) carry_sh = scan[blockIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int t0 = 0; t0 < kScanTile; t0 += 256) {
-        const int64_t j = base + t0 + threadIdx.x;
+        const int64_t j = tile0 + t0 + threadIdx.x;
         const int64_t v = j < R ? st->counts[j] : 0;
         int64_t x = v;
         for (int off = 1; off < 64; off <<= 1) {
@@ -344,12 +353,13 @@ __global__ void __launch_bounds__(256) k_scan_down(pa_state* st)
         if (threadIdx.x == 255) carry_sh = pre + x;
         __syncthreads();
     }
-    if (base + kScanTile >= R && threadIdx.x == 0) st->offsets[R] = st->R_new;
+    if (tile0 + kScanTile >= R && threadIdx.x == 0) st->offsets[R] = st->R_new;
 }
 
 // source replica of each new replica: largest j with offsets[j] <= r'
-__global__ void __launch_bounds__(256) k_src(pa_state* st)
+__global__ void __launch_bounds__(256) k_src(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (rn >= st->R_new) return;
@@ -365,8 +375,9 @@ __global__ void __launch_bounds__(256) k_src(pa_state* st)
 }
 
 // u8 gather: one thread per 16 bytes of a destination row
-__global__ void __launch_bounds__(256) k_gather_u8(pa_state* st)
+__global__ void __launch_bounds__(256) k_gather_u8(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int per_row = st->row_stride / 16;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -383,24 +394,35 @@ __global__ void __launch_bounds__(256) k_gather_u8(pa_state* st)
 }
 
 // bit-packed gather: lane = destination replica, loop over rows; a row word of replica j sits
-// at (j/64 * n_rows + rho) * 64 + j mod 64
+// at (j/64 * n_rows + rho) * 64 + j mod 64 (row words of 1, 2 or 4 bytes by lattice size)
 template <typename Wt>
-__global__ void __launch_bounds__(256) k_gather_bits(pa_state* st, int n_rows)
+__device__ inline void gather_rows(const pa_state* st, int64_t j, int64_t rn, int n_rows)
 {
+    const int cur = st->cur;
+    const Wt* a = (const Wt*)st->spins[cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
+    Wt* b = (Wt*)st->spins[cur ^ 1] + ((rn >> 6) * n_rows) * 64 + (rn & 63);
+    for (int rho = 0; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
+}
+
+__global__ void __launch_bounds__(256) k_gather_bits(pa_state* base)
+{
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (rn >= st->R_new) return;
     const int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
     const int64_t j = src[rn];
-    const int cur = st->cur;
-    const Wt* a = (const Wt*)st->spins[cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
-    Wt* b = (Wt*)st->spins[cur ^ 1] + ((rn >> 6) * n_rows) * 64 + (rn & 63);
-    for (int rho = 0; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
-    st->energy[cur ^ 1][rn] = st->energy[cur][j];
+    const int n_rows = st->dim == 1 ? (st->N + 31) / 32 : st->L * st->L;
+    const int WB = st->dim == 1 ? 4 : (st->L <= 8 ? 1 : (st->L <= 16 ? 2 : 4));
+    if (WB == 1) gather_rows<uint8_t>(st, j, rn, n_rows);
+    else if (WB == 2) gather_rows<uint16_t>(st, j, rn, n_rows);
+    else gather_rows<uint32_t>(st, j, rn, n_rows);
+    st->energy[st->cur ^ 1][rn] = st->energy[st->cur][j];
 }
 
-__global__ void k_finish(pa_state* st, ResampleParams p)
+__global__ void k_finish(pa_state* base, ResampleParams p)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
@@ -413,49 +435,61 @@ __global__ void k_finish(pa_state* st, ResampleParams p)
     st->record[p.k].R = (double)st->R_new;
 }
 
-int launch_hist(const pa_run& run, hipStream_t s)
+// Launch shapes cover the largest run of the call; grid.y indexes the runs, whose states
+// are contiguous (state r at runs[0].state + r).  A single run is n = 1.
+struct BatchShape {
+    int64_t cap_max = 0, bins_max = 0, stride_max = 0;
+};
+
+static BatchShape batch_shape(const pa_run* runs, int n)
 {
-    pa_sizes sz;
-    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.capacity, run.n_records, &sz);
-    if (rc != PA_OK) return rc;
-    const size_t hist_lds = sz.n_bins <= 16384 ? (size_t)sz.n_bins * 4 : 0;
-    const unsigned hist_blocks = (unsigned)std::min<int64_t>(1024, (run.capacity + 255) / 256);
-    hipLaunchKernelGGL(k_hist_clear, dim3(32), dim3(256), 0, s, run.state);
-    hipLaunchKernelGGL(k_hist, dim3(hist_blocks), dim3(256), hist_lds, s, run.state);
+    BatchShape b;
+    for (int r = 0; r < n; ++r) {
+        pa_sizes sz;
+        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].capacity, runs[r].n_records, &sz);
+        b.cap_max = std::max(b.cap_max, runs[r].capacity);
+        b.bins_max = std::max(b.bins_max, sz.n_bins);
+        b.stride_max = std::max(b.stride_max, sz.row_stride);
+    }
+    return b;
+}
+
+int launch_hist(const pa_run* runs, int n, hipStream_t s)
+{
+    const BatchShape b = batch_shape(runs, n);
+    const size_t hist_lds = b.bins_max <= 16384 ? (size_t)b.bins_max * 4 : 0;
+    const unsigned hist_blocks = (unsigned)std::min<int64_t>(1024, (b.cap_max + 255) / 256);
+    hipLaunchKernelGGL(k_hist_clear, dim3(32, n), dim3(256), 0, s, runs[0].state);
+    hipLaunchKernelGGL(k_hist, dim3(hist_blocks, n), dim3(256), hist_lds, s, runs[0].state);
     return PA_OK;
 }
 
-int launch_resample(const pa_run& run, const pa_step& step, hipStream_t s)
+int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s)
 {
-    pa_sizes sz;
-    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.capacity, run.n_records, &sz);
-    if (rc != PA_OK) return rc;
+    const BatchShape b = batch_shape(runs, n);
     ResampleParams p;
     p.beta_from = step.beta_from;
     p.beta_to = step.beta_to;
     p.R_target = step.R_target;
     p.w = step.weights;
     p.k = step.k;
-    const unsigned cap_blocks = (unsigned)((run.capacity + 255) / 256);
-    const int n_scan = (int)((run.capacity + kScanTile - 1) / kScanTile);
-    launch_hist(run, s);
-    hipLaunchKernelGGL(k_normalise, dim3(1), dim3(256), 0, s, run.state, p);
-    hipLaunchKernelGGL(k_copies, dim3(cap_blocks), dim3(256), 0, s, run.state, (int32_t)step.k);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan), dim3(256), 0, s, run.state);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, run.state, n_scan);
-    hipLaunchKernelGGL(k_scan_down, dim3(n_scan), dim3(256), 0, s, run.state);
-    hipLaunchKernelGGL(k_src, dim3(cap_blocks), dim3(256), 0, s, run.state);
-    if (run.layout == PA_U8) {
-        const int64_t threads = run.capacity * (sz.row_stride / 16);
-        hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.state);
+    pa_state* base = runs[0].state;
+    const unsigned cap_blocks = (unsigned)((b.cap_max + 255) / 256);
+    const unsigned n_scan = (unsigned)((b.cap_max + kScanTile - 1) / kScanTile);
+    launch_hist(runs, n, s);
+    hipLaunchKernelGGL(k_normalise, dim3(1, n), dim3(256), 0, s, base, p);
+    hipLaunchKernelGGL(k_copies, dim3(cap_blocks, n), dim3(256), 0, s, base, (int32_t)step.k);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, n), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, n), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_scan_down, dim3(n_scan, n), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_src, dim3(cap_blocks, n), dim3(256), 0, s, base);
+    if (runs[0].layout == PA_U8) {
+        const int64_t threads = b.cap_max * (b.stride_max / 16);
+        hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256), n), dim3(256), 0, s, base);
     } else {
-        const int n_rows = run.dim == 1 ? (run.L + 31) / 32 : run.L * run.L;
-        const int W = run.dim == 1 ? 32 : (run.L <= 8 ? 8 : (run.L <= 16 ? 16 : 32));
-        if (W == 8) hipLaunchKernelGGL(k_gather_bits<uint8_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
-        else if (W == 16) hipLaunchKernelGGL(k_gather_bits<uint16_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
-        else hipLaunchKernelGGL(k_gather_bits<uint32_t>, dim3(cap_blocks), dim3(256), 0, s, run.state, n_rows);
+        hipLaunchKernelGGL(k_gather_bits, dim3(cap_blocks, n), dim3(256), 0, s, base);
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, run.state, p);
+    hipLaunchKernelGGL(k_finish, dim3(1, n), dim3(1), 0, s, base, p);
     return hip_status(hipGetLastError());
 }
 

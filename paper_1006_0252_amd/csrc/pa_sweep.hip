@@ -493,26 +493,34 @@ static SweepConfig fast_config(int L)
 
 static SweepConfig g_override = {0, 0};
 
-int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
+int build_sweep_params(const pa_step& step, int z, SweepParams* pp)
 {
-    SweepParams p;
+    SweepParams& p = *pp;
     memset(&p, 0, sizeof(p));
-    const int z = 2 * run.dim;
     uint64_t T[8];
     uint8_t always[8];
     build_thresholds(step.beta_to, z, T, always);
-    bool zero = true;
     for (int c = 0; c <= z; ++c) {
         p.T64[c] = T[c];
         p.thi[c] = always[c] ? 0x10000u : (uint32_t)(T[c] >> 48);
-        if (c > z / 2 && p.thi[c] != 0) zero = false;
     }
     p.t0 = step.t0;
     p.n_sweeps = step.n_sweeps;
+    return PA_OK;
+}
+
+int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
+{
+    SweepParams p;
+    const int z = 2 * run.dim;
+    build_sweep_params(step, z, &p);
+    bool zero = true;
+    for (int c = z / 2 + 1; c <= z; ++c)
+        if (p.thi[c] != 0) zero = false;
     SweepConfig cfg = default_config(run.dim, run.L);
     if (g_override.lpr) cfg = g_override;
     int st;
-    if (run.dim == 3 && run.L % 4 == 0 && run.L <= 16) {
+    if (fast_sweep_supported(run.dim, run.L)) {
         SweepConfig fc = g_override.lpr ? g_override : fast_config(run.L);
         st = launch_sweep_fast(run, p, fc.lpr, fc.wpb, s);
         if (st != PA_OK) return st;

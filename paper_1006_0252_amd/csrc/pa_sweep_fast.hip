@@ -1,9 +1,12 @@
-// Metropolis sweeps of the cube for L = 4, 8, 12, 16: the same sample as the generic kernel
+// Metropolis sweeps of the cube for even L <= 16: the same sample as the generic kernel
 // (same Philox fields, same acceptance rule), laid out for the vector ALU.
 //
 //  - lane = replica; a replica's rows (one 16-bit word per (y, z) row, bit x = spin) sit in
 //    LDS, planes of L rows per z; LPR lanes share a replica by taking L/LPR planes each;
-//  - the y loop of a plane is unrolled, so every neighbour row is an immediate LDS offset;
+//  - the y loop of a plane is unrolled, so every neighbour row is an immediate LDS offset, and
+//    the Philox field of every site is a compile-time constant given the plane's phase (the
+//    position of its first half-site inside an 8-site Philox chunk: 0 when L = 0 mod 4,
+//    0/2/4/6 by plane when L = 2 mod 4);
 //  - per row, the six bond words J s s (bit-parallel over x) feed a bit-sliced adder giving
 //    c = number of bonds with J s_i s_j = -1 (dE = 4c - 12); c <= 3 flips outright;
 //  - the 16-bit first look of each site against its threshold is specialised by regime:
@@ -12,7 +15,13 @@
 //    MODE 0: general.  Possible ties are flagged per lane and resolved exactly with the
 //    48 low bits in a separate (rare) path;
 //  - energies are recomputed once per launch from bond popcounts.
+//
+// Two launch forms share the per-tile code: one block of waves per group of replicas of one
+// run (k_sweep3f), and a persistent kernel for a batch of runs (k_sweep_batch), one wave per
+// block pulling (run, tile) items from a device work counter.
 #include <string.h>
+
+#include <algorithm>
 
 #include "pa_common.h"
 #include "pa_sweep_util.h"
@@ -50,40 +59,29 @@ static __device__ __noinline__ uint32_t resolve_row(uint32_t c0, uint32_t c1, ui
 template <int L, int LPR>
 struct FastLayout {
     static constexpr int NR = L * L;
+    static constexpr int H = L / 2;
     static constexpr int RPW = 64 / LPR;
     static constexpr int PL = L / LPR;                          // planes per lane
     static constexpr int PADW = LPR == 4 ? 8 : 0;               // u16 padding per plane (bank stagger)
     static constexpr int PSTRIDE = L * RPW + PADW;              // u16 per plane
     static constexpr int JPAD = LPR == 4 ? 4 : 0;
     static constexpr int JSTRIDE = L * 8 + JPAD;                // dwords of coupling masks per plane
-    static constexpr size_t lds_bytes(int wpb) { return (size_t)L * JSTRIDE * 4 + (size_t)wpb * L * PSTRIDE * 2; }
+    static constexpr int JDWORDS = L * JSTRIDE;
+    static constexpr int ROW_BYTES = L * PSTRIDE * 2;           // one wave's rows
+    static constexpr size_t lds_bytes(int wpb) { return (size_t)JDWORDS * 4 + (size_t)wpb * ROW_BYTES; }
 };
 
-template <int L, int LAYOUT, int LPR, int MODE>
-__global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st, SweepParams p, FastThr th)
+// lanes per replica used for each lattice size (L = 2 mod 4 needs one lane per replica so
+// that the Philox phase of a plane is uniform over the wave)
+__host__ __device__ constexpr int batch_lpr(int L) { return L % 4 != 0 ? 1 : (L >= 12 ? 4 : (L >= 8 ? 2 : 1)); }
+
+// coupling masks per row, entries +x, +y, +z, -x, -y, -z bonds with J = -1
+template <int L, int LPR>
+__device__ void build_jtab(const pa_state* st, uint32_t* jtab, int tid, int nthr)
 {
     using F = FastLayout<L, LPR>;
-    constexpr int NR = F::NR, H = L / 2, RPW = F::RPW, PL = F::PL;
-    constexpr int PSTRIDE = F::PSTRIDE, JSTRIDE = F::JSTRIDE;
-    constexpr uint32_t MASK = (1u << L) - 1u;
-    constexpr int WB = L <= 8 ? 1 : 2;  // bytes of a row word in the bit-packed layout
-    static_assert(L % 4 == 0 && L <= 16 && L % LPR == 0, "fast sweep geometry");
-    if (st->status) return;  // sticky error: the population stays as it is
-    extern __shared__ uint32_t lds[];
-    uint32_t* jtab = lds;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int q = lane % RPW, j = lane / RPW;
-    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + L * JSTRIDE) + wave * (L * PSTRIDE);
-    const int wpb = blockDim.x >> 6;
-    const int64_t R = st->R;
-    const int cur = st->cur;
-    const int64_t rbase = ((int64_t)blockIdx.x * wpb + wave) * RPW;
-    const int64_t r = rbase + q;
-    const bool valid = r < R;
-
-    // coupling masks per row, entries +x, +y, +z, -x, -y, -z bonds with J = -1
     const int8_t* J = st->J;
-    for (int rho = threadIdx.x; rho < NR; rho += blockDim.x) {
+    for (int rho = tid; rho < F::NR; rho += nthr) {
         const int y = rho % L, z = rho / L;
         const int ym = (y + L - 1) % L, zm = (z + L - 1) % L;
         uint32_t m[6] = {0, 0, 0, 0, 0, 0};
@@ -97,114 +95,161 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
             m[4] |= (uint32_t)(J[3 * (x + L * (ym + L * z)) + 1] < 0) << x;
             m[5] |= (uint32_t)(J[3 * (x + L * (y + L * zm)) + 2] < 0) << x;
         }
-        uint32_t* e = jtab + z * JSTRIDE + y * 8;
+        uint32_t* e = jtab + z * F::JSTRIDE + y * 8;
         for (int k = 0; k < 6; ++k) e[k] = m[k];
         e[6] = 0;
         e[7] = 0;
     }
+}
 
-    // this lane's planes z = j PL .. j PL + PL - 1 into LDS
-    if (rbase < R) {
-        for (int t = 0; t < PL; ++t) {
-            const int z = j * PL + t;
-            uint16_t* P = rows + z * PSTRIDE + q;
-            for (int y = 0; y < L; ++y) {
-                const int rho = y + L * z;
-                uint32_t v;
-                if (LAYOUT == PA_BITS64) {
-                    const uint8_t* a = (const uint8_t*)st->spins[cur] + (((r >> 6) * NR + rho) * 64 + (r & 63)) * WB;
-                    v = WB == 1 ? *a : *(const uint16_t*)a;
-                } else {
-                    const uint32_t* a = (const uint32_t*)((const uint8_t*)st->spins[cur] + r * st->row_stride + rho * L);
-                    v = 0;
+struct PlaneCtx {
+    uint32_t rr, ctr2, k0, k1;
+    int d5, d6;
+    bool valid;
+};
+
+// one colour of one plane z of this lane's replica
+template <int L, int LPR, int MODE, int PH>
+__device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jtab, int z, int q, int col,
+                                             const PlaneCtx& c, const FastThr& th)
+{
+    using F = FastLayout<L, LPR>;
+    constexpr int H = F::H, RPW = F::RPW, PSTRIDE = F::PSTRIDE;
+    constexpr uint32_t MASK = (1u << L) - 1u;
+    const int zp = (z + 1 == L) ? 0 : z + 1;
+    const int zm = (z == 0) ? L - 1 : z - 1;
+    uint16_t* P0 = rows + z * PSTRIDE + q;
+    const uint16_t* Pp = rows + zp * PSTRIDE + q;
+    const uint16_t* Pm = rows + zm * PSTRIDE + q;
+    const uint32_t* JT = jtab + z * F::JSTRIDE;
+    const uint32_t cb = (uint32_t)((z * (L * H)) >> 3);  // Philox call holding the plane's first half-site
+    const int p0 = (col + z) & 1;                        // x parity of colour col at y = 0
+    const uint32_t cmA = (p0 ? 0xAAAAAAAAu : 0x55555555u) & MASK;
+    const uint32_t cmB = (~cmA) & MASK;
+    const uint32_t thi4 = th.thi4;
+    uint4v rnd = {0, 0, 0, 0};
 #pragma unroll
-                    for (int d = 0; d < L / 4; ++d) v |= pack4(a[d]) << (4 * d);
-                }
-                P[y * RPW] = (uint16_t)v;
+    for (int y = 0; y < L; ++y) {
+        const uint32_t own = P0[y * RPW];
+        const uint32_t yp = P0[((y + 1) % L) * RPW];
+        const uint32_t ym = P0[((y + L - 1) % L) * RPW];
+        const uint32_t zpv = Pp[y * RPW];
+        const uint32_t zmv = Pm[y * RPW];
+        const uint32_t* jr = JT + y * 8;
+        const uint32_t dup = own | (own << L);
+        const uint32_t b0 = own ^ (dup >> 1) ^ jr[0];
+        const uint32_t b1 = own ^ yp ^ jr[1];
+        const uint32_t b2 = own ^ zpv ^ jr[2];
+        const uint32_t b3 = own ^ (dup >> (L - 1)) ^ jr[3];
+        const uint32_t b4 = own ^ ym ^ jr[4];
+        const uint32_t b5 = own ^ zmv ^ jr[5];
+        const uint32_t s1 = b0 ^ b1 ^ b2, k1c = (b0 & b1) | (b2 & (b0 ^ b1));
+        const uint32_t s2 = b3 ^ b4 ^ b5, k2c = (b3 & b4) | (b5 & (b3 ^ b4));
+        const uint32_t c0 = s1 ^ s2, k3c = s1 & s2;
+        const uint32_t c1 = k1c ^ k2c ^ k3c;
+        const uint32_t c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
+        const uint32_t colmask = (y & 1) ? cmB : cmA;
+        const int par = p0 ^ (y & 1);
+        uint32_t acc = 0;
+        bool tie = false;
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const int hm = PH + y * H + m;  // position counted from the start of call cb
+            if (hm % 8 == 0 || (y == 0 && m == 0))
+                rnd = philox10(cb + (uint32_t)(hm / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+            const uint32_t u = field16(rnd, hm & 7);
+            const int xb = 2 * m + par;
+            if (MODE == 2) {
+                tie |= (u == 0u);
+            } else if (MODE == 1) {
+                acc |= (uint32_t)(u < thi4) << xb;
+                tie |= (u == thi4) | (u == 0u);
+            } else {
+                // class bits at x as 0 / -1 masks select the threshold differences
+                const int q0 = __builtin_amdgcn_sbfe((int)c0, xb, 1);
+                const int q1 = __builtin_amdgcn_sbfe((int)c1, xb, 1);
+                const uint32_t thi = (uint32_t)((int)thi4 + (q0 & c.d5) + (q1 & c.d6));
+                acc |= (uint32_t)(u < thi) << xb;
+                tie |= (u == thi);
             }
         }
+        uint32_t flip;
+        if (MODE == 2) flip = colmask & ~c2;
+        else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+        else flip = colmask & (~c2 | acc);
+        if (tie) {
+            const uint32_t cand = c2 & colmask;
+            const int rho = y + L * z;
+            const uint32_t racc = resolve_row(c0, c1, cand, par, rho * H, H, L * rho, c.rr, c.ctr2, c.k0, c.k1, th);
+            flip = colmask & (~c2 | racc);
+        }
+        if (!c.valid) flip = 0;
+        P0[y * RPW] = (uint16_t)(own ^ flip);
     }
-    __syncthreads();
-    if (rbase >= R) return;
+}
 
-    const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
-    const uint32_t rr = (uint32_t)r;
-    const uint32_t thi4 = th.thi4;
-    const int d5 = (int)th.thi5 - (int)th.thi4, d6 = (int)th.thi6 - (int)th.thi4;
+// N_S sweeps of the RPW replicas rbase .. rbase + RPW - 1 of one run (one wave)
+template <int L, int LAYOUT, int LPR, int MODE>
+__device__ void sweep_tile(const pa_state* st, int64_t rbase, const uint32_t* jtab, uint16_t* rows, int lane,
+                           const SweepParams& p, const FastThr& th)
+{
+    using F = FastLayout<L, LPR>;
+    constexpr int NR = F::NR, H = F::H, RPW = F::RPW, PL = F::PL, PSTRIDE = F::PSTRIDE;
+    constexpr uint32_t MASK = (1u << L) - 1u;
+    constexpr int WB = L <= 8 ? 1 : 2;  // bytes of a row word in the bit-packed layout
+    static_assert(L % 2 == 0 && L <= 16 && L % LPR == 0, "fast sweep geometry");
+    static_assert(L % 4 == 0 || LPR == 1, "L = 2 mod 4 needs one lane per replica");
+    const int q = lane % RPW, j = lane / RPW;
+    const int64_t R = st->R;
+    const int cur = st->cur;
+    const int64_t r = rbase + q;
+    PlaneCtx c;
+    c.valid = r < R;
+    c.rr = (uint32_t)r;
+    c.k0 = (uint32_t)st->seed;
+    c.k1 = (uint32_t)(st->seed >> 32);
+    c.d5 = (int)th.thi5 - (int)th.thi4;
+    c.d6 = (int)th.thi6 - (int)th.thi4;
+
+    // this lane's planes z = j PL .. j PL + PL - 1 into LDS
+    for (int t = 0; t < PL; ++t) {
+        const int z = j * PL + t;
+        uint16_t* P = rows + z * PSTRIDE + q;
+        for (int y = 0; y < L; ++y) {
+            const int rho = y + L * z;
+            uint32_t v = 0;
+            if (LAYOUT == PA_BITS64) {
+                const uint8_t* a = (const uint8_t*)st->spins[cur] + (((r >> 6) * NR + rho) * 64 + (r & 63)) * WB;
+                v = WB == 1 ? *a : *(const uint16_t*)a;
+            } else if (L % 4 == 0) {
+                const uint32_t* a = (const uint32_t*)((const uint8_t*)st->spins[cur] + r * st->row_stride + rho * L);
+#pragma unroll
+                for (int d = 0; d < L / 4; ++d) v |= pack4(a[d]) << (4 * d);
+            } else {
+                const uint8_t* a = (const uint8_t*)st->spins[cur] + r * st->row_stride + rho * L;
+#pragma unroll
+                for (int x = 0; x < L; ++x) v |= (uint32_t)(a[x] & 1) << x;
+            }
+            P[y * RPW] = (uint16_t)v;
+        }
+    }
+    wave_sync();
 
     for (int s = 0; s < p.n_sweeps; ++s) {
         const int64_t t_sweep = p.t0 + s;
         for (int col = 0; col < 2; ++col) {
-            const uint32_t ctr2 = (uint32_t)(2 * t_sweep + col);
+            c.ctr2 = (uint32_t)(2 * t_sweep + col);
             for (int t = 0; t < PL; ++t) {
                 const int z = j * PL + t;
-                const int zp = (z + 1 == L) ? 0 : z + 1;
-                const int zm = (z == 0) ? L - 1 : z - 1;
-                uint16_t* P0 = rows + z * PSTRIDE + q;
-                const uint16_t* Pp = rows + zp * PSTRIDE + q;
-                const uint16_t* Pm = rows + zm * PSTRIDE + q;
-                const uint32_t* JT = jtab + z * JSTRIDE;
-                const uint32_t cb = (uint32_t)(z * (L * H / 8));  // first Philox call of the plane
-                const int p0 = (col + z) & 1;                      // x parity of colour col at y = 0
-                const uint32_t cmA = (p0 ? 0xAAAAAAAAu : 0x55555555u) & MASK;
-                const uint32_t cmB = (~cmA) & MASK;
-                uint4v rnd = {0, 0, 0, 0};
-#pragma unroll
-                for (int y = 0; y < L; ++y) {
-                    const uint32_t own = P0[y * RPW];
-                    const uint32_t yp = P0[((y + 1) % L) * RPW];
-                    const uint32_t ym = P0[((y + L - 1) % L) * RPW];
-                    const uint32_t zpv = Pp[y * RPW];
-                    const uint32_t zmv = Pm[y * RPW];
-                    const uint32_t* jr = JT + y * 8;
-                    const uint32_t dup = own | (own << L);
-                    const uint32_t b0 = own ^ (dup >> 1) ^ jr[0];
-                    const uint32_t b1 = own ^ yp ^ jr[1];
-                    const uint32_t b2 = own ^ zpv ^ jr[2];
-                    const uint32_t b3 = own ^ (dup >> (L - 1)) ^ jr[3];
-                    const uint32_t b4 = own ^ ym ^ jr[4];
-                    const uint32_t b5 = own ^ zmv ^ jr[5];
-                    const uint32_t s1 = b0 ^ b1 ^ b2, k1c = (b0 & b1) | (b2 & (b0 ^ b1));
-                    const uint32_t s2 = b3 ^ b4 ^ b5, k2c = (b3 & b4) | (b5 & (b3 ^ b4));
-                    const uint32_t c0 = s1 ^ s2, k3c = s1 & s2;
-                    const uint32_t c1 = k1c ^ k2c ^ k3c;
-                    const uint32_t c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
-                    const uint32_t colmask = (y & 1) ? cmB : cmA;
-                    const int par = p0 ^ (y & 1);
-                    uint32_t acc = 0;
-                    bool tie = false;
-#pragma unroll
-                    for (int m = 0; m < H; ++m) {
-                        const int hm = y * H + m;
-                        if (hm % 8 == 0) rnd = philox10(cb + (uint32_t)(hm / 8), rr, ctr2, kTagMet, k0, k1);
-                        const uint32_t u = field16(rnd, hm & 7);
-                        const int xb = 2 * m + par;
-                        if (MODE == 2) {
-                            tie |= (u == 0u);
-                        } else if (MODE == 1) {
-                            acc |= (uint32_t)(u < thi4) << xb;
-                            tie |= (u == thi4) | (u == 0u);
-                        } else {
-                            // class bits at x as 0 / -1 masks select the threshold differences
-                            const int q0 = __builtin_amdgcn_sbfe((int)c0, xb, 1);
-                            const int q1 = __builtin_amdgcn_sbfe((int)c1, xb, 1);
-                            const uint32_t thi = (uint32_t)((int)thi4 + (q0 & d5) + (q1 & d6));
-                            acc |= (uint32_t)(u < thi) << xb;
-                            tie |= (u == thi);
-                        }
+                if constexpr (L % 4 == 0) {
+                    plane_update<L, LPR, MODE, 0>(rows, jtab, z, q, col, c, th);
+                } else {
+                    switch ((z * (L * H)) & 7) {
+                        case 0: plane_update<L, LPR, MODE, 0>(rows, jtab, z, q, col, c, th); break;
+                        case 2: plane_update<L, LPR, MODE, 2>(rows, jtab, z, q, col, c, th); break;
+                        case 4: plane_update<L, LPR, MODE, 4>(rows, jtab, z, q, col, c, th); break;
+                        default: plane_update<L, LPR, MODE, 6>(rows, jtab, z, q, col, c, th); break;
                     }
-                    uint32_t flip;
-                    if (MODE == 2) flip = colmask & ~c2;
-                    else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
-                    else flip = colmask & (~c2 | acc);
-                    if (tie) {
-                        const uint32_t cand = c2 & colmask;
-                        const int rho = y + L * z;
-                        const uint32_t racc = resolve_row(c0, c1, cand, par, rho * H, H, L * rho, rr, ctr2, k0, k1, th);
-                        flip = colmask & (~c2 | racc);
-                    }
-                    if (!valid) flip = 0;
-                    P0[y * RPW] = (uint16_t)(own ^ flip);
                 }
             }
             // the other colour reads these rows next (other lanes of the replica too)
@@ -219,7 +264,7 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
         const int zp = (z + 1 == L) ? 0 : z + 1;
         const uint16_t* P0 = rows + z * PSTRIDE + q;
         const uint16_t* Pp = rows + zp * PSTRIDE + q;
-        const uint32_t* JT = jtab + z * JSTRIDE;
+        const uint32_t* JT = jtab + z * F::JSTRIDE;
 #pragma unroll
         for (int y = 0; y < L; ++y) {
             const uint32_t own = P0[y * RPW];
@@ -233,7 +278,7 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
     for (int off = RPW; off < 64; off <<= 1) neg += __shfl_xor(neg, off, 64);
 
     // rows back to HBM
-    if (valid) {
+    if (c.valid) {
         for (int t = 0; t < PL; ++t) {
             const int z = j * PL + t;
             const uint16_t* P = rows + z * PSTRIDE + q;
@@ -244,17 +289,121 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
                     uint8_t* a = (uint8_t*)st->spins[cur] + (((r >> 6) * NR + rho) * 64 + (r & 63)) * WB;
                     if (WB == 1) *a = (uint8_t)v;
                     else *(uint16_t*)a = (uint16_t)v;
-                } else {
+                } else if (L % 4 == 0) {
                     uint32_t* a = (uint32_t*)((uint8_t*)st->spins[cur] + r * st->row_stride + rho * L);
 #pragma unroll
                     for (int d = 0; d < L / 4; ++d) a[d] = unpack4(v >> (4 * d));
+                } else {
+                    uint8_t* a = (uint8_t*)st->spins[cur] + r * st->row_stride + rho * L;
+#pragma unroll
+                    for (int x = 0; x < L; ++x) a[x] = (uint8_t)((v >> x) & 1u);
                 }
             }
         }
         if (j == 0) st->energy[cur][r] = st->n_bonds - 2 * neg;
     }
+    wave_sync();
 }
 
+// ------------------------------------------------------------------ one run
+template <int L, int LAYOUT, int LPR, int MODE>
+__global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st, SweepParams p, FastThr th)
+{
+    using F = FastLayout<L, LPR>;
+    if (st->status) return;  // sticky error: the population stays as it is
+    extern __shared__ uint32_t lds[];
+    build_jtab<L, LPR>(st, lds, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::JDWORDS) + wave * (F::ROW_BYTES / 2);
+    const int64_t rbase = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * F::RPW;
+    if (rbase >= st->R) return;
+    sweep_tile<L, LAYOUT, LPR, MODE>(st, rbase, lds, rows, lane, p, th);
+}
+
+// ------------------------------------------------------------------ a batch of runs
+// The runs' states are contiguous (state r at base + r).  Work items are (run, tile of RPW
+// replicas); k_batch_tiles lays them out in the order given by the host (position p holds run
+// order[p]) and resets the work counter; k_sweep_batch waves take items in that order.
+constexpr int kMaxBatch = 1024;
+
+struct BatchOrder {
+    uint16_t run[kMaxBatch];
+};
+
+__global__ void __launch_bounds__(256) k_batch_tiles(pa_state* base, int n_runs, BatchOrder order)
+{
+    int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
+    __shared__ int64_t cnt[kMaxBatch];
+    for (int pos = threadIdx.x; pos < n_runs; pos += blockDim.x) {
+        const pa_state* st = base + order.run[pos];
+        const int rpw = 64 / batch_lpr(st->L);
+        cnt[pos] = st->status ? 0 : (st->R + rpw - 1) / rpw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int pos = 0; pos < n_runs; ++pos) {
+            tb[pos] = acc;
+            acc += cnt[pos];
+        }
+        tb[n_runs] = acc;
+        base->work_counter = 0;
+    }
+}
+
+template <int L, int LAYOUT, int MODE>
+__device__ __forceinline__ void batch_tile(const pa_state* st, int64_t local, bool rebuild, uint32_t* lds, int lane,
+                                           const SweepParams& p, const FastThr& th)
+{
+    constexpr int LPR = batch_lpr(L);
+    using F = FastLayout<L, LPR>;
+    if (rebuild) {
+        build_jtab<L, LPR>(st, lds, lane, 64);
+        wave_sync();
+    }
+    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::JDWORDS);
+    sweep_tile<L, LAYOUT, LPR, MODE>(st, local * F::RPW, lds, rows, lane, p, th);
+}
+
+template <int LAYOUT, int MODE>
+__global__ void __launch_bounds__(64) k_sweep_batch(pa_state* base, int n_runs, BatchOrder order, SweepParams p,
+                                                    FastThr th)
+{
+    extern __shared__ uint32_t lds[];
+    const int lane = threadIdx.x;
+    const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
+    const int64_t total = tb[n_runs];
+    int cached = -1;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&base->work_counter, 1u);
+        t = __shfl(t, 0, 64);
+        if ((int64_t)t >= total) break;  // every wave leaves once the items are taken
+        int lo = 0, hi = n_runs;          // tb[lo] <= t < tb[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tb[mid] <= (int64_t)t) lo = mid;
+            else hi = mid;
+        }
+        const int run = order.run[lo];
+        const pa_state* st = base + run;
+        const int64_t local = (int64_t)t - tb[lo];
+        const bool rebuild = run != cached;
+        cached = run;
+        switch (st->L) {
+            case 4: batch_tile<4, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 6: batch_tile<6, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 8: batch_tile<8, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 10: batch_tile<10, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 12: batch_tile<12, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 14: batch_tile<14, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            default: batch_tile<16, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
 static size_t fast_lds_limit()
 {
     static size_t cached = 0;
@@ -266,6 +415,34 @@ static size_t fast_lds_limit()
         lim = (size_t)v;
     cached = lim;
     return lim;
+}
+
+static int cu_count()
+{
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        cached = v;
+    else
+        cached = 256;
+    return cached;
+}
+
+static FastThr make_thr(const SweepParams& p, int* mode)
+{
+    FastThr th;
+    th.thi4 = p.thi[4];
+    th.thi5 = p.thi[5];
+    th.thi6 = p.thi[6];
+    th.T4 = p.T64[4];
+    th.T5 = p.T64[5];
+    th.T6 = p.T64[6];
+    *mode = 0;
+    if (th.thi4 == 0 && th.thi5 == 0 && th.thi6 == 0) *mode = 2;
+    else if (th.thi5 == 0 && th.thi6 == 0) *mode = 1;
+    return th;
 }
 
 template <int L, int LAYOUT, int LPR, int MODE>
@@ -294,9 +471,13 @@ template <int L, int LAYOUT>
 static int fast_p(const pa_run& run, const SweepParams& p, const FastThr& th, int mode, int lpr, int wpb,
                   hipStream_t s)
 {
-    if (lpr == 4 && L % 4 == 0) return fast_m<L, LAYOUT, (L % 4 == 0 ? 4 : 1)>(run, p, th, mode, wpb, s);
-    if (lpr == 2) return fast_m<L, LAYOUT, 2>(run, p, th, mode, wpb, s);
-    return fast_m<L, LAYOUT, 1>(run, p, th, mode, wpb, s);
+    if constexpr (L % 4 != 0) {
+        return fast_m<L, LAYOUT, 1>(run, p, th, mode, wpb, s);
+    } else {
+        if (lpr == 4) return fast_m<L, LAYOUT, 4>(run, p, th, mode, wpb, s);
+        if (lpr == 2) return fast_m<L, LAYOUT, 2>(run, p, th, mode, wpb, s);
+        return fast_m<L, LAYOUT, 1>(run, p, th, mode, wpb, s);
+    }
 }
 
 template <int L>
@@ -307,27 +488,92 @@ static int fast_l(const pa_run& run, const SweepParams& p, const FastThr& th, in
                                : fast_p<L, PA_BITS64>(run, p, th, mode, lpr, wpb, s);
 }
 
+bool fast_sweep_supported(int dim, int L) { return dim == 3 && L % 2 == 0 && L >= 4 && L <= 16; }
+
 // returns PA_ERR_ARG when the lattice is not one the fast kernel handles
 int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s)
 {
-    if (run.dim != 3 || run.L % 4 != 0 || run.L > 16) return PA_ERR_ARG;
-    FastThr th;
-    th.thi4 = p.thi[4];
-    th.thi5 = p.thi[5];
-    th.thi6 = p.thi[6];
-    th.T4 = p.T64[4];
-    th.T5 = p.T64[5];
-    th.T6 = p.T64[6];
-    int mode = 0;
-    if (th.thi4 == 0 && th.thi5 == 0 && th.thi6 == 0) mode = 2;
-    else if (th.thi5 == 0 && th.thi6 == 0) mode = 1;
+    if (!fast_sweep_supported(run.dim, run.L)) return PA_ERR_ARG;
+    int mode;
+    const FastThr th = make_thr(p, &mode);
     switch (run.L) {
         case 4: return fast_l<4>(run, p, th, mode, lpr, wpb, s);
+        case 6: return fast_l<6>(run, p, th, mode, lpr, wpb, s);
         case 8: return fast_l<8>(run, p, th, mode, lpr, wpb, s);
+        case 10: return fast_l<10>(run, p, th, mode, lpr, wpb, s);
         case 12: return fast_l<12>(run, p, th, mode, lpr, wpb, s);
+        case 14: return fast_l<14>(run, p, th, mode, lpr, wpb, s);
         case 16: return fast_l<16>(run, p, th, mode, lpr, wpb, s);
         default: return PA_ERR_ARG;
     }
 }
 
+static size_t batch_lds_bytes(int L)
+{
+    switch (L) {
+        case 4: return FastLayout<4, batch_lpr(4)>::lds_bytes(1);
+        case 6: return FastLayout<6, batch_lpr(6)>::lds_bytes(1);
+        case 8: return FastLayout<8, batch_lpr(8)>::lds_bytes(1);
+        case 10: return FastLayout<10, batch_lpr(10)>::lds_bytes(1);
+        case 12: return FastLayout<12, batch_lpr(12)>::lds_bytes(1);
+        case 14: return FastLayout<14, batch_lpr(14)>::lds_bytes(1);
+        default: return FastLayout<16, batch_lpr(16)>::lds_bytes(1);
+    }
+}
+
+static int g_batch_blocks_per_cu = 8;
+static int g_batch_order = 1;  // 0: as given, 1: larger lattices first
+
+// one persistent launch for n_runs contiguous runs (3D, even L in 4..16, one layout)
+int launch_sweep_batch(const pa_run* runs, int n_runs, const SweepParams& p, hipStream_t s)
+{
+    if (n_runs > kMaxBatch) return PA_ERR_ARG;
+    BatchOrder order;
+    for (int r = 0; r < n_runs; ++r) order.run[r] = (uint16_t)r;
+    if (g_batch_order == 1)
+        std::stable_sort(order.run, order.run + n_runs, [&](uint16_t a, uint16_t b) {
+            const double ca = (double)runs[a].L * runs[a].L * runs[a].L * 64 / batch_lpr(runs[a].L);
+            const double cb = (double)runs[b].L * runs[b].L * runs[b].L * 64 / batch_lpr(runs[b].L);
+            return ca > cb;
+        });
+    size_t lds = 0;
+    int64_t tiles_max = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        lds = std::max(lds, batch_lds_bytes(runs[r].L));
+        tiles_max += (runs[r].capacity + 63) / (64 / batch_lpr(runs[r].L));
+    }
+    if (lds > fast_lds_limit()) return PA_ERR_ARG;
+    int mode;
+    const FastThr th = make_thr(p, &mode);
+    hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(256), 0, s, runs[0].state, n_runs, order);
+    const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles_max);
+    const dim3 grid((unsigned)std::max<int64_t>(1, blocks)), block(64);
+    pa_state* base = runs[0].state;
+    if (runs[0].layout == PA_U8) {
+        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch<PA_U8, 2>), grid, block, lds, s, base, n_runs, order, p, th);
+        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch<PA_U8, 1>), grid, block, lds, s, base, n_runs, order, p, th);
+        else hipLaunchKernelGGL((k_sweep_batch<PA_U8, 0>), grid, block, lds, s, base, n_runs, order, p, th);
+    } else {
+        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 2>), grid, block, lds, s, base, n_runs, order, p, th);
+        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 1>), grid, block, lds, s, base, n_runs, order, p, th);
+        else hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 0>), grid, block, lds, s, base, n_runs, order, p, th);
+    }
+    return PA_OK;
+}
+
 }  // namespace pa
+
+// persistent batch schedule for the autotuner: blocks per CU (1..32) and work order
+// (0: runs as given, 1: larger lattices first); 0, 0 restores the defaults
+extern "C" int pa_set_batch_config(int blocks_per_cu, int order)
+{
+    if (blocks_per_cu == 0 && order == 0) {
+        pa::g_batch_blocks_per_cu = 8;
+        pa::g_batch_order = 1;
+        return PA_OK;
+    }
+    if (blocks_per_cu < 1 || blocks_per_cu > 32 || order < 0 || order > 1) return PA_ERR_ARG;
+    pa::g_batch_blocks_per_cu = blocks_per_cu;
+    pa::g_batch_order = order;
+    return PA_OK;
+}

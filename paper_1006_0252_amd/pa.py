@@ -82,6 +82,11 @@ SIGNATURES = {
     "pa_thresholds": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, P, P]),
     "pa_ladder_table": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "pa_set_sweep_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "pa_set_batch_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "pa_graph_begin": (ctypes.c_int, [P]),
+    "pa_graph_end": (ctypes.c_int, [P, ctypes.POINTER(P)]),
+    "pa_graph_launch": (ctypes.c_int, [P, P]),
+    "pa_graph_destroy": (ctypes.c_int, [P]),
 }
 
 
@@ -162,6 +167,10 @@ def set_sweep_config(lanes_per_replica=0, waves_per_block=0):
     check(lib().pa_set_sweep_config(lanes_per_replica, waves_per_block), "pa_set_sweep_config")
 
 
+def set_batch_config(blocks_per_cu=0, order=0):
+    check(lib().pa_set_batch_config(blocks_per_cu, order), "pa_set_batch_config")
+
+
 # ------------------------------------------------------------------ runs
 def linear_schedule(n_temps, beta_max=5.0):
     """beta_k = beta_max k / (n_temps - 1), k = 0 .. n_temps - 1 (beta_0 = 0)."""
@@ -203,7 +212,7 @@ class Run:
     """One population-annealing run: caller-owned torch buffers described by a pa_run."""
 
     def __init__(self, dim, L, R0, seed, disorder_seed, n_records, capacity=None, layout="u8", device="cuda",
-                 stream=None):
+                 stream=None, state_ptr=None):
         import torch
 
         self.dim, self.L, self.R0 = dim, L, int(R0)
@@ -227,7 +236,7 @@ class Run:
         self.offsets = buf(s.offsets_bytes)
         self.work = buf(s.work_bytes)
         self.record = buf(s.record_bytes)
-        self.state = buf(s.state_bytes)
+        self.state = None if state_ptr is not None else buf(s.state_bytes)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         r = pa_run()
         r.dim, r.L, r.layout, r.n_records = dim, L, self.layout, n_records
@@ -240,7 +249,7 @@ class Run:
         r.offsets = self.offsets.data_ptr()
         r.work = self.work.data_ptr()
         r.record = self.record.data_ptr()
-        r.state = self.state.data_ptr()
+        r.state = state_ptr if state_ptr is not None else self.state.data_ptr()
         r.stream = self.stream.cuda_stream
         self.desc = r
         self.n_records = n_records
@@ -314,6 +323,96 @@ class Run:
         c = self.counts[: 4 * R].cpu().numpy().view(np.int32).copy()
         o = self.offsets[: 8 * (R + 1)].cpu().numpy().view(np.int64).copy()
         return c, o
+
+
+class Batch:
+    """Many runs whose device states are consecutive: every pa_* call covers all of them with
+    one launch per kernel (the sweep as one persistent launch over (run, tile) work items)."""
+
+    def __init__(self, specs, n_records, layout="bits64", device="cuda", stream=None, capacity_factor=1.25):
+        """specs: list of dicts with dim, L, R0, seed, disorder_seed."""
+        import torch
+
+        self.n = len(specs)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        self.states = torch.zeros(self.n * 256 + 256, dtype=torch.uint8, device=device)
+        base = self.states.data_ptr()
+        self.runs = []
+        for r, sp in enumerate(specs):
+            cap = int(np.ceil(sp["R0"] * capacity_factor / 64.0)) * 64 + 64
+            self.runs.append(Run(sp["dim"], sp["L"], sp["R0"], sp["seed"], sp["disorder_seed"], n_records,
+                                 capacity=cap, layout=layout, device=device, stream=self.stream,
+                                 state_ptr=base + 256 * r))
+        self.arr = (pa_run * self.n)(*[r.desc for r in self.runs])
+        self.n_records = n_records
+
+    def init(self, J_list=None):
+        if J_list is None:
+            check(lib().pa_init_couplings(self.arr, self.n, None), "pa_init_couplings")
+        else:
+            self._J = [np.ascontiguousarray(J, np.int8) for J in J_list]
+            ptrs = (P * self.n)(*[J.ctypes.data_as(P).value for J in self._J])
+            check(lib().pa_init_couplings(self.arr, self.n, ctypes.cast(ptrs, P)), "pa_init_couplings")
+        return self
+
+    def resample(self, step):
+        check(lib().pa_resample(self.arr, self.n, ctypes.byref(step)), "pa_resample")
+
+    def sweep(self, step):
+        check(lib().pa_sweep(self.arr, self.n, ctypes.byref(step)), "pa_sweep")
+
+    def measure(self, pairs=False):
+        if pairs:
+            p = np.array([r ^ 1 for r in range(self.n)], dtype=np.int32)
+            check(lib().pa_measure(self.arr, self.n, _np(p)), "pa_measure")
+        else:
+            check(lib().pa_measure(self.arr, self.n, None), "pa_measure")
+
+    def free_energy(self, out_tensor):
+        check(lib().pa_free_energy(self.arr, self.n, out_tensor.data_ptr()), "pa_free_energy")
+
+    def status(self):
+        flags = np.zeros(self.n, np.int32)
+        code = lib().pa_status(self.arr, self.n, _np(flags))
+        return code, flags
+
+    def records(self):
+        return np.stack([r.records() for r in self.runs])
+
+    def step(self, sched, k, pairs=False):
+        st = sched.step(k)
+        self.resample(st)
+        self.sweep(st)
+        self.measure(pairs)
+
+    def capture(self, sched, ks, pairs=False):
+        """HIP graph of the steps ks (resample, sweep, measure each) on the batch's stream."""
+        import torch
+
+        with torch.cuda.stream(self.stream):
+            check(lib().pa_graph_begin(self.stream.cuda_stream), "pa_graph_begin")
+            try:
+                for k in ks:
+                    self.step(sched, k, pairs)
+            finally:
+                g = P()
+                rc = lib().pa_graph_end(self.stream.cuda_stream, ctypes.byref(g))
+            check(rc, "pa_graph_end")
+        return Graph(g, self.stream)
+
+
+class Graph:
+    def __init__(self, handle, stream):
+        self.handle = handle
+        self.stream = stream
+
+    def launch(self):
+        check(lib().pa_graph_launch(self.handle, self.stream.cuda_stream), "pa_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib().pa_graph_destroy(self.handle)
+            self.handle = None
 
 
 def measure(runs, partner=None):

@@ -1,0 +1,170 @@
+"""Batched runs (one launch per kernel for many runs of uneven size), HIP graph capture of
+a schedule, and the persistent sweep's schedule options: all must give exactly the sample
+that the runs give one by one, and the oracle's sample."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1006_0252_amd import pa  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def specs_mixed():
+    # pairs (0,1), (2,3), ... share the lattice and couplings (overlap partners)
+    Ls = [6, 6, 10, 10, 8, 8, 16, 16, 12, 12, 4, 4]
+    R0s = [300, 21, 130, 200, 257, 64, 70, 130, 95, 66, 64, 100]
+    return [dict(dim=3, L=L, R0=R, seed=100 + i, disorder_seed=7 + i // 2) for i, (L, R) in enumerate(zip(Ls, R0s))]
+
+
+def solo_runs(specs, n_records, layout, caps):
+    runs = []
+    for sp, cap in zip(specs, caps):
+        r = pa.Run(sp["dim"], sp["L"], sp["R0"], sp["seed"], sp["disorder_seed"], n_records, capacity=cap,
+                   layout=layout, device=DEV)
+        r.init()
+        runs.append(r)
+    return runs
+
+
+def compare(batch, solos, k):
+    for i, (b, s) in enumerate(zip(batch.runs, solos)):
+        sb, Eb = b.population()
+        ss, Es = s.population()
+        assert np.array_equal(sb, ss) and np.array_equal(Eb, Es), f"run {i} population differs after step {k}"
+        rb, rs = b.records(), s.records()
+        assert np.array_equal(rb, rs), f"run {i} records differ after step {k}"
+
+
+@pytest.mark.parametrize("layout", ["bits64", "u8"])
+def test_batch_equals_solo_mixed_sizes(layout):
+    specs = specs_mixed()
+    nT, ns = 9, 3
+    betas = [3.5 * k / (nT - 1) for k in range(nT)]  # crosses all three first-look regimes
+    note(f"batch vs solo {layout}")
+    batch = pa.Batch(specs, nT, layout=layout, device=DEV).init()
+    solos = solo_runs(specs, nT, layout, [r.capacity for r in batch.runs])
+    n_bins = max(r.n_bins for r in batch.runs)
+    sched = pa.Schedule(betas, ns, n_bins, device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k, pairs=True)
+        st = sched.step(k)
+        for i, r in enumerate(solos):
+            r.resample(st)
+            r.sweep(st)
+        pa.measure(solos, [i ^ 1 for i in range(len(solos))])
+        if k in (1, 4, nT - 1):
+            compare(batch, solos, k)
+    code, flags = batch.status()
+    assert code == pa.PA_OK and not flags.any()
+    fe = torch.zeros(len(specs), dtype=torch.float64, device=DEV)
+    batch.free_energy(fe)
+    rec = batch.records()
+    assert np.allclose(fe.cpu().numpy(), rec[:, -1, 2], rtol=1e-15)
+
+
+def test_batch_matches_oracle():
+    specs = [dict(dim=3, L=6, R0=150, seed=31, disorder_seed=4), dict(dim=3, L=10, R0=90, seed=32, disorder_seed=5),
+             dict(dim=3, L=8, R0=130, seed=33, disorder_seed=4)]
+    nT, ns = 6, 4
+    betas = [2.0 * k / (nT - 1) for k in range(nT)]
+    note("batch vs oracle")
+    batch = pa.Batch(specs, nT, layout="bits64", device=DEV).init()
+    sched = pa.Schedule(betas, ns, max(r.n_bins for r in batch.runs), device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k)
+    for sp, run in zip(specs, batch.runs):
+        J = o.couplings(3, sp["L"], sp["disorder_seed"])
+        st, rec_o, s_o, E_o = o.run(3, sp["L"], J, sp["seed"], sp["R0"], betas, ns, capacity=run.capacity)
+        assert st == 0
+        s, E = run.population()
+        assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+        rec = run.records()
+        assert np.allclose(rec[:, 2], rec_o[:, 3], rtol=1e-12, atol=0)
+
+
+def test_graph_replays_equal_eager():
+    specs = specs_mixed()[:8]
+    nT, ns = 6, 2
+    betas = [3.0 * k / (nT - 1) for k in range(nT)]
+    note("graph capture")
+    stream = torch.cuda.Stream(DEV)
+    gb = pa.Batch(specs, nT, layout="bits64", device=DEV, stream=stream)
+    eb = pa.Batch(specs, nT, layout="bits64", device=DEV)
+    sched = pa.Schedule(betas, ns, max(r.n_bins for r in gb.runs), device=DEV)
+    gb.init()
+    torch.cuda.synchronize()
+    graph = gb.capture(sched, range(1, nT), pairs=True)
+    for replay in range(3):
+        note(f"graph replay {replay}")
+        gb.init()  # eager work between replays
+        graph.launch()
+        eb.init()
+        for k in range(1, nT):
+            eb.step(sched, k, pairs=True)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(gb.runs, eb.runs)):
+            sa, Ea = a.population()
+            sb, Eb = b.population()
+            assert np.array_equal(sa, sb) and np.array_equal(Ea, Eb), f"replay {replay} run {i}"
+            assert np.array_equal(a.records(), b.records()), f"replay {replay} run {i} records"
+
+
+def test_batch_schedules_give_same_sample():
+    specs = specs_mixed()
+    nT = 3
+    betas = [0.0, 0.6, 1.4]
+    ref = None
+    try:
+        for bpc, order in ((8, 1), (1, 0), (3, 1), (16, 0)):
+            note(f"batch schedule blocks_per_cu={bpc} order={order}")
+            pa.set_batch_config(bpc, order)
+            b = pa.Batch(specs, nT, layout="bits64", device=DEV).init()
+            sched = pa.Schedule(betas, 3, max(r.n_bins for r in b.runs), device=DEV)
+            for k in range(1, nT):
+                b.step(sched, k)
+            pops = [r.population() for r in b.runs]
+            if ref is None:
+                ref = pops
+            else:
+                for (s1, e1), (s2, e2) in zip(ref, pops):
+                    assert np.array_equal(s1, s2) and np.array_equal(e1, e2)
+    finally:
+        pa.set_batch_config(0, 0)
+
+
+def test_batch_error_is_isolated():
+    # one run overflows its capacity: it freezes with the flag, the others carry on
+    specs = [dict(dim=3, L=8, R0=200, seed=5, disorder_seed=1), dict(dim=3, L=8, R0=200, seed=6, disorder_seed=1)]
+    note("batch error isolation")
+    b = pa.Batch(specs, 3, layout="bits64", device=DEV, capacity_factor=1.0).init()
+    sched = pa.Schedule([0.0, 0.1, 0.2], 2, b.runs[0].n_bins, device=DEV, R_targets=[0, 200.0, 200.0])
+    st = sched.step(1)
+    b.resample(st)
+    b.sweep(st)
+    code, flags = b.status()
+    # R_target = 200 with capacity 320: both fit; now ask one run for too many by a solo step
+    assert code == pa.PA_OK
+    big = pa.Schedule([0.1, 0.2], 1, b.runs[0].n_bins, device=DEV, R_targets=[0, 5000.0])
+    b.runs[0].resample(big.step(1))
+    s1_before, _ = b.runs[1].population()
+    st2 = sched.step(2)
+    b.resample(st2)
+    b.sweep(st2)
+    code, flags = b.status()
+    assert flags[0] & pa.PA_FLAG_CAPACITY and flags[1] == 0
+    assert b.runs[1].query().k == 2
