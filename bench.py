@@ -51,7 +51,34 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
+    p.add_argument("--workload", default="L16", choices=["L16", "batched"],
+                   help="L16: the throughput configuration (default); batched: 256 runs in one graph")
     return p.parse_args()
+
+
+def bench_batched(args):
+    """256 runs (64 realisations x 4 seeds, L in {6,8,10}, R0 in [1e4,1e5]) annealed together:
+    one persistent sweep launch per step, the whole schedule one HIP graph; value = attempts/s
+    of the graph replay (steps = the 100 temperature steps)."""
+    from paper_1006_0252_amd import ensemble, workloads
+
+    specs = workloads.batched_specs()
+    r = ensemble.run_batched(specs, workloads.C3_TEMPS, workloads.C3_SWEEPS, tune=True, graph=True)
+    w = r["weighted"]
+    out = {
+        "metric": METRIC, "value": r["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
+        "steps": workloads.C3_TEMPS - 1, "warmup": 0,
+        "ms_per_step": r["seconds"] / (workloads.C3_TEMPS - 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched_64x4_L6-10_R1e4-1e5", "runs": len(specs), "n_temps": workloads.C3_TEMPS,
+                   "n_sweeps": workloads.C3_SWEEPS, "layout": "bits64", "graph": True,
+                   "tuned_blocks_per_cu_order": r["tuned"]},
+        "batched": {"attempts": r["attempts"], "seconds": r["seconds"],
+                    "mean_var_betaF": float(np.mean(w["var_betaF"])),
+                    "max_var_betaF": float(np.max(w["var_betaF"])),
+                    "mean_gamma": float(np.mean(w["gamma"])), "mean_binder": float(np.mean(w["binder"]))},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(L, R0, n_sweeps, target_s):
@@ -88,6 +115,9 @@ def main():
     from paper_1006_0252_amd import pa
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     dev = "cuda:0"
     n_steps = args.n_temps - 1
     if args.warmup + args.steps > n_steps:

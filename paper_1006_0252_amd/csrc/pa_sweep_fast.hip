@@ -352,16 +352,16 @@ __global__ void __launch_bounds__(256) k_batch_tiles(pa_state* base, int n_runs,
     }
 }
 
+// one work item: the coupling table of the item's run is rebuilt for every item (a few
+// hundred byte loads per lane against ~10^5 attempts per lane)
 template <int L, int LAYOUT, int MODE>
-__device__ __forceinline__ void batch_tile(const pa_state* st, int64_t local, bool rebuild, uint32_t* lds, int lane,
+__device__ __forceinline__ void batch_tile(const pa_state* st, int64_t local, uint32_t* lds, int lane,
                                            const SweepParams& p, const FastThr& th)
 {
     constexpr int LPR = batch_lpr(L);
     using F = FastLayout<L, LPR>;
-    if (rebuild) {
-        build_jtab<L, LPR>(st, lds, lane, 64);
-        wave_sync();
-    }
+    build_jtab<L, LPR>(st, lds, lane, 64);
+    wave_sync();
     uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::JDWORDS);
     sweep_tile<L, LAYOUT, LPR, MODE>(st, local * F::RPW, lds, rows, lane, p, th);
 }
@@ -374,7 +374,6 @@ __global__ void __launch_bounds__(64) k_sweep_batch(pa_state* base, int n_runs, 
     const int lane = threadIdx.x;
     const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
     const int64_t total = tb[n_runs];
-    int cached = -1;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(&base->work_counter, 1u);
@@ -389,16 +388,14 @@ __global__ void __launch_bounds__(64) k_sweep_batch(pa_state* base, int n_runs, 
         const int run = order.run[lo];
         const pa_state* st = base + run;
         const int64_t local = (int64_t)t - tb[lo];
-        const bool rebuild = run != cached;
-        cached = run;
         switch (st->L) {
-            case 4: batch_tile<4, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            case 6: batch_tile<6, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            case 8: batch_tile<8, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            case 10: batch_tile<10, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            case 12: batch_tile<12, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            case 14: batch_tile<14, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
-            default: batch_tile<16, LAYOUT, MODE>(st, local, rebuild, lds, lane, p, th); break;
+            case 4: batch_tile<4, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            case 6: batch_tile<6, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            case 8: batch_tile<8, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            case 10: batch_tile<10, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            case 12: batch_tile<12, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            case 14: batch_tile<14, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
+            default: batch_tile<16, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
         }
     }
 }

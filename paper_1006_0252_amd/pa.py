@@ -190,6 +190,8 @@ class Schedule:
         tabs = np.stack([fill_weights(self.betas[k] - self.betas[k - 1], n_bins) for k in range(1, len(self.betas))]) \
             if len(self.betas) > 1 else np.zeros((0, n_bins))
         self.weights = torch.from_numpy(tabs).to(device)
+        # the tables are read by kernels on the runs' streams: finish the copy first
+        torch.cuda.current_stream(device).synchronize()
 
     def __len__(self):
         return len(self.betas)
@@ -237,7 +239,11 @@ class Run:
         self.work = buf(s.work_bytes)
         self.record = buf(s.record_bytes)
         self.state = None if state_ptr is not None else buf(s.state_bytes)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        alloc_stream = torch.cuda.current_stream(device)
+        self.stream = stream if stream is not None else alloc_stream
+        if self.stream != alloc_stream:
+            # the zero fills of the buffers above run on the allocating stream: order them first
+            self.stream.wait_stream(alloc_stream)
         r = pa_run()
         r.dim, r.L, r.layout, r.n_records = dim, L, self.layout, n_records
         r.capacity, r.R0 = self.capacity, self.R0

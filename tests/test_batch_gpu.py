@@ -168,3 +168,67 @@ def test_batch_error_is_isolated():
     code, flags = b.status()
     assert flags[0] & pa.PA_FLAG_CAPACITY and flags[1] == 0
     assert b.runs[1].query().k == 2
+
+
+def test_ensemble_weighted_averages_and_autotuner():
+    # a reduced batched configuration: 3 realisations x 4 seeds, graph-captured schedule,
+    # tuned persistent schedule; device weighted averages equal the oracle's host ones
+    from paper_1006_0252_amd import ensemble, workloads
+
+    specs = workloads.batched_specs(n_realizations=3, R0_range=(300, 900), gen_seed=11)
+    note("ensemble reduced batched configuration")
+    r = ensemble.run_batched(specs, 11, 3, device=DEV, tune=True, graph=True)
+    rec = r["records"]
+    w = r["weighted"]
+    k = 10
+    for n, d in enumerate(w["realizations"]):
+        idx = [i for i, sp in enumerate(specs) if sp["realization"] == d]
+        x = rec[idx, k, 2]
+        R = np.array([specs[i]["R0"] for i in idx], dtype=np.float64)
+        ref = o.weighted_average(x, rec[idx, k, 6][:, None], R)
+        assert abs(w["E_bar"][n] - ref["A_bar"][0]) <= 1e-12 * abs(ref["A_bar"][0])
+        assert abs(w["minus_betaF_bar"][n] - ref["minus_betaF_bar"]) <= 1e-12 * abs(ref["minus_betaF_bar"])
+        assert abs(w["var_betaF"][n] - ref["var"]) <= 1e-12 * max(1.0, ref["var"])
+        xp = x[0::2] + x[1::2]
+        Rp = R[0::2] * R[1::2]
+        refq = o.weighted_average(xp, rec[np.array(idx)[0::2], k, 9][:, None], Rp)
+        assert abs(w["q2"][n] - refq["A_bar"][0]) <= 1e-12
+    assert r["tuned"] in [(b, o_) for b in (2, 4, 8, 16) for o_ in (0, 1)]
+
+
+def test_full_batched_configuration_sampled_parity():
+    # the batched configuration at full size (256 runs, L in {6, 8, 10}, R0 in [1e4, 1e5]): one
+    # persistent sweep and one batched resampling, checked against the oracle on sampled
+    # replicas of every 8th run and on all copy numbers of those runs
+    from paper_1006_0252_amd import workloads
+
+    specs = workloads.batched_specs()
+    note("full batched configuration: init + sweep")
+    b = pa.Batch(specs, 3, layout="bits64", device=DEV).init()
+    betas = [0.0, 0.05, 0.1]
+    sched = pa.Schedule(betas, 10, max(r.n_bins for r in b.runs), device=DEV)
+    b.sweep(sched.step(1))
+    code, _ = b.status()
+    assert code == pa.PA_OK
+    E1 = {}
+    for i in range(0, len(specs), 8):
+        sp = specs[i]
+        J = o.couplings(3, sp["L"], sp["disorder_seed"])
+        idx = np.array([0, 63, 64, 129, sp["R0"] // 2, sp["R0"] - 1])
+        sg = b.runs[i].replica_spins(idx)
+        Eg = b.runs[i].energies()
+        E1[i] = Eg
+        for k, r in enumerate(idx):
+            so, Eo = o.init_replicas(3, sp["L"], J, sp["seed"], int(r), 1)
+            o.sweep_replicas(3, sp["L"], J, sp["seed"], 0.05, int(r), so, Eo, 0, 10)
+            assert np.array_equal(sg[k], so[0]) and Eg[r] == Eo[0], f"run {i} replica {r}"
+    note("full batched configuration: resample")
+    b.resample(sched.step(2))
+    code, _ = b.status()
+    assert code == pa.PA_OK
+    for i in range(0, len(specs), 8):
+        sp = specs[i]
+        st, counts_o, S_o, lnQ_o, _ = o.copy_numbers(sp["seed"], 2, betas[1], betas[2], sp["R0"], E1[i])
+        c, off = b.runs[i].counts_offsets(sp["R0"])
+        assert np.array_equal(c, counts_o), f"copy numbers of run {i}"
+        assert b.runs[i].records()[2][3] == S_o
