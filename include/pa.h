@@ -284,6 +284,74 @@ int pa_set_batch_config(int blocks_per_cu, int order);
  * order of acceptance tests per site); it exists for the autotuner. */
 int pa_set_sweep_config(int lanes_per_replica, int waves_per_block);
 
+/* ------------------------------------------------- learned temperature steps (extension)
+ * The paper leaves the temperature schedule to the user: any sequence of temperatures gives
+ * an exact method (Sec. II), and Var(beta F~) across runs measures its quality (Sec. III).
+ * These calls let a small network propose each step dbeta from statistics of the population
+ * itself.  Resampling is unchanged, so any proposed schedule is an exact one; a schedule is
+ * produced on a pilot run and then frozen for the production runs, which keeps the
+ * estimators of Sec. III valid.
+ *
+ * Resampled fraction of a step: with the normalised weights tau_j of eq. wn for a step dbeta,
+ *   rho(dbeta) = 1 - (1/R~) sum_j min(1, tau_j),
+ * the total-variation distance between the population and its reweighting (0 at dbeta = 0,
+ * non-decreasing in dbeta, below 1 - fraction at the lowest energy).
+ *
+ * Network: 6 -> 64 -> 64 -> 64 -> 1, tanh hidden units, BF16 parameters, FP32 arithmetic.
+ * Inputs x = (beta, ln N, ln R~, E_mean/N, E_var/N, E_skew) (pa_features), mapped to
+ * xh = ((beta - 2.5)/2.5, (ln N - 6)/2, (ln R~ - 10)/2.5, E/N + 1, var/N - 1, skew/2).
+ * Output z; the proposed step is dbeta = softplus(z) / sigma_E with sigma_E = sqrt(N var/N),
+ * i.e. the network predicts the step in units of the energy spread.  Parameter vector
+ * (PA_MLP_PARAMS values, W[out][in] row-major): W1[64][6] @0, b1[64] @384, W2[64][64] @448,
+ * b2 @4544, W3[64][64] @4608, b3 @8704, w4[64] @8768, b4 @8832. */
+#define PA_MLP_PARAMS 8833
+#define PA_RHO_MAX 8
+
+/* Features of every run's population at its current temperature into x_dev[r][6] (device
+ * FP32): (beta, ln N, ln R~, E_mean/N, E_var/N, E_skew) from record[k], so call after
+ * pa_measure.  Asynchronous on the runs' streams. */
+int pa_features(const pa_run* runs, int n_runs, float* x_dev);
+
+/* rho(dbeta[j]) of every run's current population for n_dbeta (1..PA_RHO_MAX) host values
+ * dbeta[j] >= 0, into out_dev[r * n_dbeta + j] (device FP64).  NaN for a run with a raised
+ * status bit. */
+int pa_resampled_fraction(pa_run* runs, int n_runs, const double* dbeta, int n_dbeta, double* out_dev);
+
+/* Step labels: for each host target rho_targets[j] in [0, 1) (n_targets <= PA_RHO_MAX) the
+ * dbeta in [0, cap] with rho(dbeta) = rho_targets[j], by 64 halvings of [0, cap]; cap when
+ * rho(cap) <= rho_targets[j].  Written to out_dev[j * ld + r] (device FP64, ld >= n_runs).
+ * NaN for a run with a raised status bit. */
+int pa_rho_steps(pa_run* runs, int n_runs, const double* rho_targets, int n_targets, double cap, int64_t ld,
+                 double* out_dev);
+
+/* Proposed steps for B feature rows x[B][6] (device FP32) with BF16 parameters w (device,
+ * PA_MLP_PARAMS): dbeta[b] = min(max(softplus(z) / sigma_E, dbeta_min), dbeta_max), and
+ * dbeta_max when E_var <= 0 or the result is NaN.  0 <= dbeta_min <= dbeta_max < inf. */
+int pa_mlp_forward(const uint16_t* w, const float* x, int64_t B, float dbeta_min, float dbeta_max, float* dbeta,
+                   void* stream);
+
+/* Bytes of device work memory pa_mlp_grad needs for a batch of B samples. */
+int pa_mlp_work_bytes(int64_t B, int64_t* bytes);
+
+/* Loss and gradient of a batch: loss = (1/B) sum_b (ln softplus(z_b) - ln sigma_E,b -
+ * ln target[b])^2, the squared error of ln dbeta (samples with E_var <= 0 or a target that is
+ * not a finite positive number contribute 0); grad (device FP32 [PA_MLP_PARAMS]) by
+ * backpropagation, loss (device FP32 [1], may be NULL).  target is device FP64 [B] (labels
+ * from pa_rho_steps); work is pa_mlp_work_bytes(B) bytes of device memory.  The sums over
+ * the batch are taken in a fixed order, so the result is reproducible. */
+int pa_mlp_grad(const uint16_t* w, const float* x, const double* target, int64_t B, void* work, float* grad,
+                float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015), step number t >= 1, on n FP32 master parameters
+ * theta with moments m, v (device, zero before the first step): m = beta1 m + (1 - beta1) g,
+ * v = beta2 v + (1 - beta2) g^2, theta -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps);
+ * then w = BF16(theta), rounded to nearest, ties to even. */
+int pa_mlp_adam(float* theta, float* m, float* v, const float* grad, uint16_t* w, int64_t n, int t, float lr,
+                float beta1, float beta2, float eps, void* stream);
+
+/* out[i] = BF16 bits of x[i] (device), round to nearest, ties to even, NaN -> 0x7FC0. */
+int pa_bf16_round(const float* x, uint16_t* out, int64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

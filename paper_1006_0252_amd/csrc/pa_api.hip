@@ -216,6 +216,55 @@ int pa_free_energy(const pa_run* runs, int n_runs, double* minus_betaF_dev)
     return PA_OK;
 }
 
+int pa_features(const pa_run* runs, int n_runs, float* x_dev)
+{
+    if (!runs || n_runs <= 0 || !x_dev) return PA_ERR_ARG;
+    for (int r = 0; r < n_runs; ++r) {
+        int st = check_run(runs[r]);
+        if (st != PA_OK) return st;
+    }
+    if (batchable(runs, n_runs)) return launch_features(runs, n_runs, x_dev, (hipStream_t)runs[0].stream);
+    for (int r = 0; r < n_runs; ++r) {
+        int st = launch_features(&runs[r], 1, x_dev + (int64_t)r * 6, (hipStream_t)runs[r].stream);
+        if (st != PA_OK) return st;
+    }
+    return PA_OK;
+}
+
+// shared checks and dispatch of pa_resampled_fraction (mode 0) and pa_rho_steps (mode 1)
+static int rho_call(pa_run* runs, int n_runs, const double* args, int n_args, int mode, double cap, int64_t ld,
+                    double* out)
+{
+    if (!runs || n_runs <= 0 || !args || n_args <= 0 || n_args > PA_RHO_MAX || !out) return PA_ERR_ARG;
+    for (int j = 0; j < n_args; ++j) {
+        if (!isfinite(args[j]) || args[j] < 0.0) return PA_ERR_ARG;
+        if (mode == 1 && !(args[j] < 1.0)) return PA_ERR_ARG;
+    }
+    if (mode == 1 && (!(cap > 0.0) || !isfinite(cap) || ld < n_runs)) return PA_ERR_ARG;
+    for (int r = 0; r < n_runs; ++r) {
+        int st = check_run(runs[r]);
+        if (st != PA_OK) return st;
+    }
+    if (batchable(runs, n_runs)) return launch_rho(runs, n_runs, args, n_args, mode, cap, ld, out, (hipStream_t)runs[0].stream);
+    for (int r = 0; r < n_runs; ++r) {
+        double* o = mode == 0 ? out + (int64_t)r * n_args : out + r;
+        int st = launch_rho(&runs[r], 1, args, n_args, mode, cap, ld, o, (hipStream_t)runs[r].stream);
+        if (st != PA_OK) return st;
+    }
+    return PA_OK;
+}
+
+int pa_resampled_fraction(pa_run* runs, int n_runs, const double* dbeta, int n_dbeta, double* out_dev)
+{
+    return rho_call(runs, n_runs, dbeta, n_dbeta, 0, 0.0, 0, out_dev);
+}
+
+int pa_rho_steps(pa_run* runs, int n_runs, const double* rho_targets, int n_targets, double cap, int64_t ld,
+                 double* out_dev)
+{
+    return rho_call(runs, n_runs, rho_targets, n_targets, 1, cap, ld, out_dev);
+}
+
 int pa_weighted_average(int M, const double* x, const double* R, const double* A, int n_obs, double* A_bar,
                         double* omega, double* minus_betaF_bar, double* var, double* mean)
 {

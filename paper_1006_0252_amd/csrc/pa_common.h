@@ -116,6 +116,9 @@ int build_sweep_params(const pa_step& step, int z, SweepParams* p);
 int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
                                 double* out, hipStream_t s);
 int build_thresholds(double beta, int z, uint64_t* T, uint8_t* always);
+int launch_features(const pa_run* runs, int n, float* x, hipStream_t s);
+int launch_rho(const pa_run* runs, int n, const double* args, int n_args, int mode, double cap, int64_t ld,
+               double* out, hipStream_t s);
 int upload_ladder(hipStream_t s);
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? PA_OK : PA_ERR_HIP; }

@@ -87,6 +87,16 @@ SIGNATURES = {
     "pa_graph_end": (ctypes.c_int, [P, ctypes.POINTER(P)]),
     "pa_graph_launch": (ctypes.c_int, [P, P]),
     "pa_graph_destroy": (ctypes.c_int, [P]),
+    "pa_features": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, P]),
+    "pa_resampled_fraction": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, P, ctypes.c_int, P]),
+    "pa_rho_steps": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, P, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int64, P]),
+    "pa_mlp_forward": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
+    "pa_mlp_work_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "pa_mlp_grad": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, P, P, P]),
+    "pa_mlp_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, P]),
+    "pa_bf16_round": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
 }
 
 
