@@ -51,8 +51,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched"],
-                   help="L16: the throughput configuration (default); batched: 256 runs in one graph")
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned"],
+                   help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
+                        "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12")
+    p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
 
@@ -77,6 +79,81 @@ def bench_batched(args):
                     "mean_var_betaF": float(np.mean(w["var_betaF"])),
                     "max_var_betaF": float(np.max(w["var_betaF"])),
                     "mean_gamma": float(np.mean(w["gamma"])), "mean_binder": float(np.mean(w["binder"]))},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned(args):
+    """Learned vs fixed temperature steps on the 3D +-J cube L = 12, R0 = 2e5, 10 sweeps per
+    temperature, beta 0 -> 5, one coupling realization (disorder seed 1).
+
+    Networks (one per target resampled fraction rho* in {0.1, 0.2, 0.3, 0.5}) are trained on
+    the GPU from fixed-schedule traces of the ring (N = 64, R0 = 1000, 51 temperatures) and the
+    L = 8 cube (R0 = 5e4, 101 temperatures).  For each rho* a pilot run picks the schedule,
+    which M production runs then follow; fixed linear schedules use N_T in {51, 101, 201, 401}.
+    Per schedule: Var(beta F~) over the M runs at beta = 5 and the wall time per run T_run;
+    time to target = T_run ceil(Var / 1e-3) (+ the pilot's time for a learned schedule).
+    value = best fixed time to target / best learned time to target."""
+    import torch
+
+    from paper_1006_0252_amd import learned, pa
+
+    dev = "cuda:0"
+    L, R0, ns, M = 12, 200_000, 10, args.ensemble
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    Xt, Dt, Xv, Dv = learned.training_set(device=dev)
+    torch.cuda.synchronize()
+    t_traces = time.perf_counter() - t0
+    log(f"traces: {Xt.shape[0]} training and {Xv.shape[0]} validation samples in {t_traces:.1f} s")
+    t0 = time.perf_counter()
+    nets, logs = learned.train_networks(Xt, Dt, Xv, Dv, steps=3000, log_every=2999, device=dev)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training: 4 networks in {t_train:.1f} s; final train/validation loss " +
+        ", ".join(f"{rs}: {h[-1][1]:.4g}/{h[-1][2]:.4g}" for rs, h in logs.items()))
+    out_l, out_f = {}, {}
+    prod_steps, prod_seconds = 0, 0.0
+    for rs in learned.RHO_TARGETS:
+        betas, info = learned.pilot_schedule(nets[rs], L, R0, seed=10 ** 6, disorder_seed=1, n_sweeps=ns,
+                                             dmin=1e-4, dmax=0.25, device=dev)
+        e = learned.ensemble(betas, M, L, R0, ns, disorder_seed=1, device=dev)
+        ttt = learned.time_to_target(e["var"], e["seconds_per_run"], overhead=info["seconds"])
+        out_l[str(rs)] = dict(n_temps=len(betas), pilot_ok=info["ok"], pilot_s=info["seconds"], var=e["var"],
+                             minus_betaF_bar=e["minus_betaF_bar"], T_run_s=e["seconds_per_run"], time_to_target_s=ttt,
+                             attempts_per_s=e["attempts"] / e["seconds"])
+        prod_steps += len(betas) - 1
+        prod_seconds += e["seconds"]
+        log(f"learned rho*={rs}: {len(betas)} temperatures, Var {e['var']:.4g}, T_run {e['seconds_per_run']:.4f} s, "
+            f"time to target {ttt:.2f} s")
+    for nT in (51, 101, 201, 401):
+        e = learned.ensemble(pa.linear_schedule(nT), M, L, R0, ns, disorder_seed=1, device=dev)
+        ttt = learned.time_to_target(e["var"], e["seconds_per_run"])
+        out_f[str(nT)] = dict(n_temps=nT, var=e["var"], minus_betaF_bar=e["minus_betaF_bar"],
+                              T_run_s=e["seconds_per_run"], time_to_target_s=ttt,
+                              attempts_per_s=e["attempts"] / e["seconds"])
+        prod_steps += nT - 1
+        prod_seconds += e["seconds"]
+        log(f"fixed N_T={nT}: Var {e['var']:.4g}, T_run {e['seconds_per_run']:.4f} s, time to target {ttt:.2f} s")
+    bl = min(out_l, key=lambda k: out_l[k]["time_to_target_s"])
+    bf = min(out_f, key=lambda k: out_f[k]["time_to_target_s"])
+    ref = out_f["401"]
+    dev_sigma = {k: (v["minus_betaF_bar"] - ref["minus_betaF_bar"]) / np.sqrt(v["var"] / M + ref["var"] / M)
+                 for k, v in out_l.items()}
+    out = {
+        "metric": METRIC, "value": out_f[bf]["time_to_target_s"] / out_l[bl]["time_to_target_s"],
+        "unit": "x (fixed / learned wall time to Var(beta F)<=1e-3)", "n_gpus": 1, "steps": prod_steps,
+        "warmup": 0, "ms_per_step": prod_seconds / prod_steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32+bf16", "data": "synthetic",
+        "config": {"workload": "learned_vs_fixed_cube_L12_R200000", "L": L, "R0": R0, "n_sweeps": ns,
+                   "runs_per_schedule": M, "disorder_seed": 1, "rho_targets": list(learned.RHO_TARGETS),
+                   "fixed_n_temps": [51, 101, 201, 401], "dbeta_clamp": [1e-4, 0.25]},
+        "best_learned": {"rho_target": float(bl), **out_l[bl]}, "best_fixed": {"n_temps": int(bf), **out_f[bf]},
+        "learned": out_l, "fixed": out_f,
+        "learned_minus_reference_sigma": dev_sigma,
+        "training": {"trace_seconds": t_traces, "train_seconds": t_train, "samples": int(Xt.shape[0]),
+                     "validation_samples": int(Xv.shape[0]),
+                     "final_loss": {str(rs): [h[-1][1], h[-1][2]] for rs, h in logs.items()}},
     }
     print(json.dumps(out), flush=True)
 
@@ -117,6 +194,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1

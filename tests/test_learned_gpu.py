@@ -198,3 +198,31 @@ def test_pilot_schedule_is_valid():
     d = np.diff(betas)
     assert np.all(d > 0) and np.all(d[:-1] >= 0.01 * (1 - 1e-6)) and np.all(d[:-1] <= 0.3 * (1 + 1e-6))
     assert d[-1] <= 0.31 * (1 + 1e-6)  # the landing step may absorb a remainder below dmin
+
+
+def test_learned_schedule_beats_fixed_at_equal_steps():
+    # what the trained network gains: a network trained on ring and L = 8 traces towards
+    # rho* = 0.3 picks the schedule of an L = 6 cube on a pilot run; with the same number of
+    # temperatures, the fixed linear schedule's Var(beta F~) is far larger, and the learned
+    # ensemble's weighted free energy agrees with a long fixed-schedule ensemble's
+    note("learned vs fixed at equal steps")
+    Xr, Dr = learned.collect_traces("ring", learned.trace_specs("ring", 6, 4), device=DEV)
+    Xc, Dc = learned.collect_traces("cube8", learned.trace_specs("cube8", 6, 1), device=DEV)
+    X = torch.cat([Xr, Xc]).contiguous()
+    D = torch.cat([Dr, Dc], dim=1).contiguous()
+    j = learned.RHO_TARGETS.index(0.3)
+    net = learned.Network(learned.glorot_theta(1), device=DEV)
+    hist = net.train(X, D[j].contiguous(), 1500, log_every=1499)
+    assert hist[-1][1] < 0.02
+    L, R0, ns, M = 6, 5000, 10, 32
+    betas, info = learned.pilot_schedule(net, L, R0, seed=10 ** 6, disorder_seed=3, n_sweeps=ns, device=DEV)
+    assert info["ok"], info
+    K = len(betas)
+    e_l = learned.ensemble(betas, M, L, R0, ns, disorder_seed=3, device=DEV)
+    e_f = learned.ensemble(pa.linear_schedule(K), M, L, R0, ns, disorder_seed=3, device=DEV)
+    ref = learned.ensemble(pa.linear_schedule(401), M, L, R0, ns, disorder_seed=3, seed0=5000, device=DEV)
+    note(f"K={K} var learned {e_l['var']:.4g} fixed {e_f['var']:.4g} long fixed {ref['var']:.4g}; "
+         f"-bF learned {e_l['minus_betaF_bar']:.4f} long fixed {ref['minus_betaF_bar']:.4f}")
+    assert e_l["var"] < 0.2 * e_f["var"]
+    se = np.sqrt(e_l["var"] / M + ref["var"] / M)
+    assert abs(e_l["minus_betaF_bar"] - ref["minus_betaF_bar"]) < 5 * se + 0.01
