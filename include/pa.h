@@ -122,7 +122,7 @@ typedef struct pa_state {
     double acc;     /* sum of ln Q so far */
     double ln_omega;/* N ln 2 */
     double beta;    /* current inverse temperature */
-    uint32_t work_counter; /* work items taken by a batched sweep (used in the batch's first run) */
+    uint32_t work_counter; /* work items taken by a batched sweep (counted in the first run of each group of equal-L runs) */
     uint32_t reserved0;
     uint8_t pad[40];
 } pa_state;
@@ -273,10 +273,14 @@ int pa_graph_end(void* stream, void** graph_exec);
 int pa_graph_launch(void* graph_exec, void* stream);
 int pa_graph_destroy(void* graph_exec);
 
-/* Persistent batched sweep schedule, for the autotuner: blocks per compute unit (1..32) and
- * work order (0: runs as given, 1: larger lattices first); (0, 0) restores the defaults.
- * Results do not depend on it. */
-int pa_set_batch_config(int blocks_per_cu, int order);
+/* Batched sweep schedule, for the autotuner.  The runs of a batch are grouped by lattice size
+ * and each group is one launch over the device work list of (run, tile) items:
+ *   blocks_per_cu (1..32): resident blocks per compute unit of a persistent launch;
+ *   order: 0 groups in order of first appearance, 1 larger tiles first;
+ *   launch: 0 by size (persistent loop for L = 0 mod 4, one item per block otherwise),
+ *           1 persistent loop for every size, 2 one item per block for every size.
+ * (0, 0, 0) restores the defaults (8, 1, 0).  Results do not depend on it. */
+int pa_set_batch_config(int blocks_per_cu, int order, int launch);
 
 /* Launch shape of the sweep kernels for later calls in this process: lanes per replica
  * (1, 2 or 4; a replica's rows are split among that many lanes) and waves per block (1..4).

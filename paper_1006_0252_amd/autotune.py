@@ -9,13 +9,14 @@ bit for bit (spins and energies of every run).
 """
 from __future__ import annotations
 
-import itertools
 
 import numpy as np
 
 from . import pa
 
-BATCH_CANDIDATES = list(itertools.product((2, 4, 8, 16), (0, 1)))
+# (blocks per CU, group order, launch form) of the batched sweep
+BATCH_CANDIDATES = ([(b, o, 0) for b in (4, 8, 16) for o in (0, 1)] + [(b, 1, 1) for b in (4, 8)] +
+                    [(8, o, 2) for o in (0, 1)])
 SOLO_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (4, 2), (4, 4)]
 
 
@@ -72,8 +73,8 @@ def tune_batch(batch: "pa.Batch", step: "pa.pa_step", repeats: int = 2, verbose:
     st = batch.stream
     snap = _snapshot(batch.runs, st)
     timings, ref = {}, None
-    for bpc, order in BATCH_CANDIDATES:
-        pa.set_batch_config(bpc, order)
+    for cand in BATCH_CANDIDATES:
+        pa.set_batch_config(*cand)
 
         def one():
             batch.sweep(step)
@@ -88,10 +89,10 @@ def tune_batch(batch: "pa.Batch", step: "pa.pa_step", repeats: int = 2, verbose:
         if ref is None:
             ref = d
         elif d != ref:
-            raise RuntimeError(f"batch schedule {bpc}, {order} changed the sample")
-        timings[(bpc, order)] = t
+            raise RuntimeError(f"batch schedule {cand} changed the sample")
+        timings[cand] = t
         if verbose:
-            print(f"  blocks/CU={bpc:2d} order={order}: {t:.3f} ms", flush=True)
+            print(f"  blocks/CU={cand[0]:2d} order={cand[1]} launch={cand[2]}: {t:.3f} ms", flush=True)
     _restore(batch.runs, snap, st)
     st.synchronize()
     best = min(timings, key=timings.get)

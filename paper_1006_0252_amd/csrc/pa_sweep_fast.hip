@@ -190,7 +190,7 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
 
 // N_S sweeps of the RPW replicas rbase .. rbase + RPW - 1 of one run (one wave)
 template <int L, int LAYOUT, int LPR, int MODE>
-__device__ void sweep_tile(const pa_state* st, int64_t rbase, const uint32_t* jtab, uint16_t* rows, int lane,
+__device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, const uint32_t* jtab, uint16_t* rows, int lane,
                            const SweepParams& p, const FastThr& th)
 {
     using F = FastLayout<L, LPR>;
@@ -336,9 +336,10 @@ __global__ void __launch_bounds__(256) k_batch_tiles(pa_state* base, int n_runs,
     int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
     __shared__ int64_t cnt[kMaxBatch];
     for (int pos = threadIdx.x; pos < n_runs; pos += blockDim.x) {
-        const pa_state* st = base + order.run[pos];
+        pa_state* st = base + order.run[pos];
         const int rpw = 64 / batch_lpr(st->L);
         cnt[pos] = st->status ? 0 : (st->R + rpw - 1) / rpw;
+        st->work_counter = 0;  // a group of equal-L runs counts its items in its first run
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -348,7 +349,6 @@ __global__ void __launch_bounds__(256) k_batch_tiles(pa_state* base, int n_runs,
             acc += cnt[pos];
         }
         tb[n_runs] = acc;
-        base->work_counter = 0;
     }
 }
 
@@ -366,38 +366,57 @@ __device__ __forceinline__ void batch_tile(const pa_state* st, int64_t local, ui
     sweep_tile<L, LAYOUT, LPR, MODE>(st, local * F::RPW, lds, rows, lane, p, th);
 }
 
-template <int LAYOUT, int MODE>
-__global__ void __launch_bounds__(64) k_sweep_batch(pa_state* base, int n_runs, BatchOrder order, SweepParams p,
-                                                    FastThr th)
+// Persistent sweep of one group of equal-L runs (positions pos0 .. pos1-1 of the order): each
+// wave takes the next item of the group, finds its run by bisection of the tile offsets and
+// sweeps that tile.  One specialisation per L keeps the register budget of the one-run kernel
+// (two waves per SIMD) instead of the union of all sizes.
+template <int L, int LAYOUT, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_batch(pa_state* base, int pos0, int pos1, BatchOrder order,
+                                                    SweepParams p, FastThr th)
 {
     extern __shared__ uint32_t lds[];
     const int lane = threadIdx.x;
     const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
-    const int64_t total = tb[n_runs];
+    const int64_t first = tb[pos0], total = tb[pos1] - first;
+    pa_state* counter = base + order.run[pos0];
     for (;;) {
         uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(&base->work_counter, 1u);
+        if (lane == 0) t = atomicAdd(&counter->work_counter, 1u);
         t = __shfl(t, 0, 64);
-        if ((int64_t)t >= total) break;  // every wave leaves once the items are taken
-        int lo = 0, hi = n_runs;          // tb[lo] <= t < tb[hi]
+        if ((int64_t)t >= total) break;  // every wave leaves once the group's items are taken
+        const int64_t item = first + (int64_t)t;
+        int lo = pos0, hi = pos1;         // tb[lo] <= item < tb[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (tb[mid] <= (int64_t)t) lo = mid;
+            if (tb[mid] <= item) lo = mid;
             else hi = mid;
         }
-        const int run = order.run[lo];
-        const pa_state* st = base + run;
-        const int64_t local = (int64_t)t - tb[lo];
-        switch (st->L) {
-            case 4: batch_tile<4, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            case 6: batch_tile<6, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            case 8: batch_tile<8, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            case 10: batch_tile<10, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            case 12: batch_tile<12, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            case 14: batch_tile<14, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-            default: batch_tile<16, LAYOUT, MODE>(st, local, lds, lane, p, th); break;
-        }
+        const pa_state* st = base + order.run[lo];
+        // the lane index passes through an empty asm each item so that the tile's lane-derived
+        // addresses are not hoisted out of the item loop (they would stay live across it)
+        int lane_i = lane;
+        asm volatile("" : "+v"(lane_i));
+        batch_tile<L, LAYOUT, MODE>(st, item - tb[lo], lds, lane_i, p, th);
     }
+}
+
+// The same items with one item per block (no item loop): for sizes whose tile code does not
+// fit the register budget of the persistent loop.  Blocks past the group's items exit.
+template <int L, int LAYOUT, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_batch_grid(
+    pa_state* base, int pos0, int pos1, BatchOrder order, SweepParams p, FastThr th)
+{
+    extern __shared__ uint32_t lds[];
+    const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
+    const int64_t item = tb[pos0] + (int64_t)blockIdx.x;
+    if (item >= tb[pos1]) return;
+    int lo = pos0, hi = pos1;  // tb[lo] <= item < tb[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tb[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    batch_tile<L, LAYOUT, MODE>(base + order.run[lo], item - tb[lo], lds, threadIdx.x, p, th);
 }
 
 // ------------------------------------------------------------------ host side
@@ -520,57 +539,110 @@ static size_t batch_lds_bytes(int L)
 
 static int g_batch_blocks_per_cu = 8;
 static int g_batch_order = 1;  // 0: as given, 1: larger lattices first
+static int g_batch_launch = 0; // 0: by size, 1: persistent for every size, 2: one item per block for every size
 
-// one persistent launch for n_runs contiguous runs (3D, even L in 4..16, one layout)
+// persistent loop or one item per block: by size, the loop for L = 0 mod 4 (its tile code keeps
+// the one-run kernel's register budget inside the loop), one item per block otherwise
+static bool group_persistent(int L)
+{
+    return g_batch_launch == 1 || (g_batch_launch == 0 && L % 4 == 0);
+}
+
+template <int L, int LAYOUT>
+static void launch_group(pa_state* base, int pos0, int pos1, const BatchOrder& order, const SweepParams& p,
+                         const FastThr& th, int mode, int64_t tiles, hipStream_t s)
+{
+    const size_t lds = FastLayout<L, batch_lpr(L)>::lds_bytes(1);
+    const dim3 block(64);
+    if (group_persistent(L)) {
+        const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles)));
+        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch<L, LAYOUT, 2>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch<L, LAYOUT, 1>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+        else hipLaunchKernelGGL((k_sweep_batch<L, LAYOUT, 0>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+    } else {
+        const dim3 grid((unsigned)std::max<int64_t>(1, tiles));
+        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch_grid<L, LAYOUT, 2>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch_grid<L, LAYOUT, 1>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+        else hipLaunchKernelGGL((k_sweep_batch_grid<L, LAYOUT, 0>), grid, block, lds, s, base, pos0, pos1, order, p, th);
+    }
+}
+
+template <int LAYOUT>
+static void launch_group_L(int L, pa_state* base, int pos0, int pos1, const BatchOrder& order, const SweepParams& p,
+                           const FastThr& th, int mode, int64_t tiles, hipStream_t s)
+{
+    switch (L) {
+        case 4: launch_group<4, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        case 6: launch_group<6, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        case 8: launch_group<8, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        case 10: launch_group<10, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        case 12: launch_group<12, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        case 14: launch_group<14, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+        default: launch_group<16, LAYOUT>(base, pos0, pos1, order, p, th, mode, tiles, s); break;
+    }
+}
+
+// Persistent sweep of n_runs contiguous runs (3D, even L in 4..16, one layout): the runs are
+// grouped by lattice size (groups ordered by the cost of a tile, larger first, or by first
+// appearance), one work list over all groups, one persistent launch per group.
 int launch_sweep_batch(const pa_run* runs, int n_runs, const SweepParams& p, hipStream_t s)
 {
     if (n_runs > kMaxBatch) return PA_ERR_ARG;
-    BatchOrder order;
-    for (int r = 0; r < n_runs; ++r) order.run[r] = (uint16_t)r;
-    if (g_batch_order == 1)
-        std::stable_sort(order.run, order.run + n_runs, [&](uint16_t a, uint16_t b) {
-            const double ca = (double)runs[a].L * runs[a].L * runs[a].L * 64 / batch_lpr(runs[a].L);
-            const double cb = (double)runs[b].L * runs[b].L * runs[b].L * 64 / batch_lpr(runs[b].L);
-            return ca > cb;
-        });
-    size_t lds = 0;
-    int64_t tiles_max = 0;
+    for (int r = 0; r < n_runs; ++r)
+        if (batch_lds_bytes(runs[r].L) > fast_lds_limit()) return PA_ERR_ARG;
+    // distinct sizes in order of first appearance, then (order 1) by tile cost, larger first
+    int sizes[kMaxBatch], n_sizes = 0;
     for (int r = 0; r < n_runs; ++r) {
-        lds = std::max(lds, batch_lds_bytes(runs[r].L));
-        tiles_max += (runs[r].capacity + 63) / (64 / batch_lpr(runs[r].L));
+        bool seen = false;
+        for (int g = 0; g < n_sizes; ++g) seen = seen || sizes[g] == runs[r].L;
+        if (!seen) sizes[n_sizes++] = runs[r].L;
     }
-    if (lds > fast_lds_limit()) return PA_ERR_ARG;
+    auto tile_cost = [](int L) { return (double)L * L * L * 64 / batch_lpr(L); };
+    if (g_batch_order == 1)
+        std::stable_sort(sizes, sizes + n_sizes, [&](int a, int b) { return tile_cost(a) > tile_cost(b); });
+    BatchOrder order;
+    int group_end[kMaxBatch];
+    int64_t group_tiles[kMaxBatch];
+    int pos = 0;
+    for (int g = 0; g < n_sizes; ++g) {
+        group_tiles[g] = 0;
+        for (int r = 0; r < n_runs; ++r) {
+            if (runs[r].L != sizes[g]) continue;
+            order.run[pos++] = (uint16_t)r;
+            group_tiles[g] += (runs[r].capacity + 63) / (64 / batch_lpr(runs[r].L));
+        }
+        group_end[g] = pos;
+    }
     int mode;
     const FastThr th = make_thr(p, &mode);
-    hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(256), 0, s, runs[0].state, n_runs, order);
-    const int64_t blocks = std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles_max);
-    const dim3 grid((unsigned)std::max<int64_t>(1, blocks)), block(64);
     pa_state* base = runs[0].state;
-    if (runs[0].layout == PA_U8) {
-        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch<PA_U8, 2>), grid, block, lds, s, base, n_runs, order, p, th);
-        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch<PA_U8, 1>), grid, block, lds, s, base, n_runs, order, p, th);
-        else hipLaunchKernelGGL((k_sweep_batch<PA_U8, 0>), grid, block, lds, s, base, n_runs, order, p, th);
-    } else {
-        if (mode == 2) hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 2>), grid, block, lds, s, base, n_runs, order, p, th);
-        else if (mode == 1) hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 1>), grid, block, lds, s, base, n_runs, order, p, th);
-        else hipLaunchKernelGGL((k_sweep_batch<PA_BITS64, 0>), grid, block, lds, s, base, n_runs, order, p, th);
+    hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(256), 0, s, base, n_runs, order);
+    for (int g = 0, pos0 = 0; g < n_sizes; pos0 = group_end[g], ++g) {
+        if (runs[0].layout == PA_U8)
+            launch_group_L<PA_U8>(sizes[g], base, pos0, group_end[g], order, p, th, mode, group_tiles[g], s);
+        else
+            launch_group_L<PA_BITS64>(sizes[g], base, pos0, group_end[g], order, p, th, mode, group_tiles[g], s);
     }
     return PA_OK;
 }
 
 }  // namespace pa
 
-// persistent batch schedule for the autotuner: blocks per CU (1..32) and work order
-// (0: runs as given, 1: larger lattices first); 0, 0 restores the defaults
-extern "C" int pa_set_batch_config(int blocks_per_cu, int order)
+// batch schedule for the autotuner: blocks per CU of a persistent launch (1..32), order of the
+// size groups (0: first appearance, 1: larger tiles first), launch form (0: by size, 1: persistent
+// loop, 2: one item per block); (0, 0, 0) restores the defaults
+extern "C" int pa_set_batch_config(int blocks_per_cu, int order, int launch)
 {
-    if (blocks_per_cu == 0 && order == 0) {
+    if (blocks_per_cu == 0 && order == 0 && launch == 0) {
         pa::g_batch_blocks_per_cu = 8;
         pa::g_batch_order = 1;
+        pa::g_batch_launch = 0;
         return PA_OK;
     }
-    if (blocks_per_cu < 1 || blocks_per_cu > 32 || order < 0 || order > 1) return PA_ERR_ARG;
+    if (blocks_per_cu < 1 || blocks_per_cu > 32 || order < 0 || order > 1 || launch < 0 || launch > 2)
+        return PA_ERR_ARG;
     pa::g_batch_blocks_per_cu = blocks_per_cu;
     pa::g_batch_order = order;
+    pa::g_batch_launch = launch;
     return PA_OK;
 }

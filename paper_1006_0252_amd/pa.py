@@ -82,7 +82,7 @@ SIGNATURES = {
     "pa_thresholds": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, P, P]),
     "pa_ladder_table": (ctypes.c_int, [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "pa_set_sweep_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
-    "pa_set_batch_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "pa_set_batch_config": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "pa_graph_begin": (ctypes.c_int, [P]),
     "pa_graph_end": (ctypes.c_int, [P, ctypes.POINTER(P)]),
     "pa_graph_launch": (ctypes.c_int, [P, P]),
@@ -177,8 +177,8 @@ def set_sweep_config(lanes_per_replica=0, waves_per_block=0):
     check(lib().pa_set_sweep_config(lanes_per_replica, waves_per_block), "pa_set_sweep_config")
 
 
-def set_batch_config(blocks_per_cu=0, order=0):
-    check(lib().pa_set_batch_config(blocks_per_cu, order), "pa_set_batch_config")
+def set_batch_config(blocks_per_cu=0, order=0, launch=0):
+    check(lib().pa_set_batch_config(blocks_per_cu, order, launch), "pa_set_batch_config")
 
 
 # ------------------------------------------------------------------ runs

@@ -130,9 +130,9 @@ def test_batch_schedules_give_same_sample():
     betas = [0.0, 0.6, 1.4]
     ref = None
     try:
-        for bpc, order in ((8, 1), (1, 0), (3, 1), (16, 0)):
-            note(f"batch schedule blocks_per_cu={bpc} order={order}")
-            pa.set_batch_config(bpc, order)
+        for bpc, order, launch in ((8, 1, 0), (1, 0, 1), (3, 1, 2), (16, 0, 0), (2, 0, 1), (5, 1, 1)):
+            note(f"batch schedule blocks_per_cu={bpc} order={order} launch={launch}")
+            pa.set_batch_config(bpc, order, launch)
             b = pa.Batch(specs, nT, layout="bits64", device=DEV).init()
             sched = pa.Schedule(betas, 3, max(r.n_bins for r in b.runs), device=DEV)
             for k in range(1, nT):
@@ -144,7 +144,7 @@ def test_batch_schedules_give_same_sample():
                 for (s1, e1), (s2, e2) in zip(ref, pops):
                     assert np.array_equal(s1, s2) and np.array_equal(e1, e2)
     finally:
-        pa.set_batch_config(0, 0)
+        pa.set_batch_config(0, 0, 0)
 
 
 def test_batch_error_is_isolated():
@@ -193,7 +193,9 @@ def test_ensemble_weighted_averages_and_autotuner():
         Rp = R[0::2] * R[1::2]
         refq = o.weighted_average(xp, rec[np.array(idx)[0::2], k, 9][:, None], Rp)
         assert abs(w["q2"][n] - refq["A_bar"][0]) <= 1e-12
-    assert r["tuned"] in [(b, o_) for b in (2, 4, 8, 16) for o_ in (0, 1)]
+    from paper_1006_0252_amd import autotune
+
+    assert r["tuned"] in autotune.BATCH_CANDIDATES
 
 
 def test_full_batched_configuration_sampled_parity():
