@@ -158,6 +158,34 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_fast.hip", "paper_1006_0252_amd/csrc/pa_sweep_util.h",
+                 "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
+
+
+def sweep_source_digest():
+    """sha256 over the sources the sweep kernel is compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def sweep_traffic(path):
+    """HBM bytes per sweep launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy's readings), or None when the sweep sources changed since."""
+    try:
+        with open(path) as f:
+            tr = json.load(f)
+    except (ValueError, OSError):
+        return None
+    if tr.get("source_digest") != sweep_source_digest():
+        return None
+    return tr.get("bytes_per_launch")
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -246,13 +274,7 @@ def main():
     sweep_s = float(np.mean(sweep_ms)) * 1e-3
     per_launch_attempts = float(np.mean(R_steps)) * N * args.n_sweeps
     achieved = per_launch_attempts * OPS_PER_ATTEMPT / sweep_s
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            tr = json.load(open(args.traffic))
-            traffic = tr.get("bytes_per_launch")
-        except (ValueError, OSError):
-            traffic = None
+    traffic = sweep_traffic(args.traffic)
     out = {
         "metric": METRIC,
         "value": value,

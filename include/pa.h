@@ -279,7 +279,7 @@ int pa_graph_destroy(void* graph_exec);
  *   order: 0 groups in order of first appearance, 1 larger tiles first;
  *   launch: 0 by size (persistent loop for L = 0 mod 4, one item per block otherwise),
  *           1 persistent loop for every size, 2 one item per block for every size.
- * (0, 0, 0) restores the defaults (8, 1, 0).  Results do not depend on it. */
+ * (0, 0, 0) restores the defaults (16, 1, 0).  Results do not depend on it. */
 int pa_set_batch_config(int blocks_per_cu, int order, int launch);
 
 /* Launch shape of the sweep kernels for later calls in this process: lanes per replica

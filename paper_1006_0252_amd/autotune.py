@@ -15,8 +15,8 @@ import numpy as np
 from . import pa
 
 # (blocks per CU, group order, launch form) of the batched sweep
-BATCH_CANDIDATES = ([(b, o, 0) for b in (4, 8, 16) for o in (0, 1)] + [(b, 1, 1) for b in (4, 8)] +
-                    [(8, o, 2) for o in (0, 1)])
+BATCH_CANDIDATES = ([(b, o, 0) for b in (8, 16, 24) for o in (0, 1)] + [(b, 1, 1) for b in (8, 16)] +
+                    [(16, o, 2) for o in (0, 1)])
 SOLO_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (4, 2), (4, 4)]
 
 

@@ -211,7 +211,10 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     c.d5 = (int)th.thi5 - (int)th.thi4;
     c.d6 = (int)th.thi6 - (int)th.thi4;
 
-    // this lane's planes z = j PL .. j PL + PL - 1 into LDS
+    // this lane's planes z = j PL .. j PL + PL - 1 into LDS (plane loops here and in the write-back
+    // stay rolled: unrolled, their 64-bit row addresses are shared between the two and held live
+    // across the sweeps, which costs two thirds of the waves per SIMD)
+#pragma unroll 1
     for (int t = 0; t < PL; ++t) {
         const int z = j * PL + t;
         uint16_t* P = rows + z * PSTRIDE + q;
@@ -277,8 +280,12 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     }
     for (int off = RPW; off < 64; off <<= 1) neg += __shfl_xor(neg, off, 64);
 
-    // rows back to HBM
+    // rows back to HBM; the replica index passes through an empty asm so that the row addresses
+    // of the load above are recomputed here rather than kept live across the sweeps
+    int64_t rw = r;
+    asm volatile("" : "+v"(rw));
     if (c.valid) {
+#pragma unroll 1
         for (int t = 0; t < PL; ++t) {
             const int z = j * PL + t;
             const uint16_t* P = rows + z * PSTRIDE + q;
@@ -286,21 +293,21 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
                 const int rho = y + L * z;
                 const uint32_t v = P[y * RPW];
                 if (LAYOUT == PA_BITS64) {
-                    uint8_t* a = (uint8_t*)st->spins[cur] + (((r >> 6) * NR + rho) * 64 + (r & 63)) * WB;
+                    uint8_t* a = (uint8_t*)st->spins[cur] + (((rw >> 6) * NR + rho) * 64 + (rw & 63)) * WB;
                     if (WB == 1) *a = (uint8_t)v;
                     else *(uint16_t*)a = (uint16_t)v;
                 } else if (L % 4 == 0) {
-                    uint32_t* a = (uint32_t*)((uint8_t*)st->spins[cur] + r * st->row_stride + rho * L);
+                    uint32_t* a = (uint32_t*)((uint8_t*)st->spins[cur] + rw * st->row_stride + rho * L);
 #pragma unroll
                     for (int d = 0; d < L / 4; ++d) a[d] = unpack4(v >> (4 * d));
                 } else {
-                    uint8_t* a = (uint8_t*)st->spins[cur] + r * st->row_stride + rho * L;
+                    uint8_t* a = (uint8_t*)st->spins[cur] + rw * st->row_stride + rho * L;
 #pragma unroll
                     for (int x = 0; x < L; ++x) a[x] = (uint8_t)((v >> x) & 1u);
                 }
             }
         }
-        if (j == 0) st->energy[cur][r] = st->n_bonds - 2 * neg;
+        if (j == 0) st->energy[cur][rw] = st->n_bonds - 2 * neg;
     }
     wave_sync();
 }
@@ -537,7 +544,7 @@ static size_t batch_lds_bytes(int L)
     }
 }
 
-static int g_batch_blocks_per_cu = 8;
+static int g_batch_blocks_per_cu = 16;
 static int g_batch_order = 1;  // 0: as given, 1: larger lattices first
 static int g_batch_launch = 0; // 0: by size, 1: persistent for every size, 2: one item per block for every size
 
@@ -634,7 +641,7 @@ int launch_sweep_batch(const pa_run* runs, int n_runs, const SweepParams& p, hip
 extern "C" int pa_set_batch_config(int blocks_per_cu, int order, int launch)
 {
     if (blocks_per_cu == 0 && order == 0 && launch == 0) {
-        pa::g_batch_blocks_per_cu = 8;
+        pa::g_batch_blocks_per_cu = 16;
         pa::g_batch_order = 1;
         pa::g_batch_launch = 0;
         return PA_OK;
