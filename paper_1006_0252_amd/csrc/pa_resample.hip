@@ -395,13 +395,24 @@ __global__ void __launch_bounds__(256) k_gather_u8(pa_state* base)
 
 // bit-packed gather: lane = destination replica, loop over rows; a row word of replica j sits
 // at (j/64 * n_rows + rho) * 64 + j mod 64 (row words of 1, 2 or 4 bytes by lattice size)
+// (16 loads in flight per lane: one dependent load-store pair per row leaves the copy latency-
+// bound, a few hundred bytes in flight per wave against the microseconds of HBM latency)
 template <typename Wt>
 __device__ inline void gather_rows(const pa_state* st, int64_t j, int64_t rn, int n_rows)
 {
+    constexpr int U = 16;
     const int cur = st->cur;
     const Wt* a = (const Wt*)st->spins[cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
     Wt* b = (Wt*)st->spins[cur ^ 1] + ((rn >> 6) * n_rows) * 64 + (rn & 63);
-    for (int rho = 0; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
+    int rho = 0;
+    for (; rho + U <= n_rows; rho += U) {
+        Wt v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = a[(int64_t)(rho + u) * 64];
+#pragma unroll
+        for (int u = 0; u < U; ++u) b[(int64_t)(rho + u) * 64] = v[u];
+    }
+    for (; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
 }
 
 __global__ void __launch_bounds__(256) k_gather_bits(pa_state* base)

@@ -104,7 +104,6 @@ __device__ void build_jtab(const pa_state* st, uint32_t* jtab, int tid, int nthr
 
 struct PlaneCtx {
     uint32_t rr, ctr2, k0, k1;
-    int d5, d6;
     bool valid;
 };
 
@@ -165,10 +164,11 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
                 acc |= (uint32_t)(u < thi4) << xb;
                 tie |= (u == thi4) | (u == 0u);
             } else {
-                // class bits at x as 0 / -1 masks select the threshold differences
-                const int q0 = __builtin_amdgcn_sbfe((int)c0, xb, 1);
-                const int q1 = __builtin_amdgcn_sbfe((int)c1, xb, 1);
-                const uint32_t thi = (uint32_t)((int)thi4 + (q0 & c.d5) + (q1 & c.d6));
+                // class bits at x as 0 / -1 masks select the threshold (class 4 + c0 + 2 c1; c0 and
+                // c1 are never both set at a candidate site, and non-candidates are masked later)
+                const uint32_t q0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xb, 1);
+                const uint32_t q1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xb, 1);
+                const uint32_t thi = (q1 & th.thi6) | (~q1 & ((q0 & th.thi5) | (~q0 & thi4)));
                 acc |= (uint32_t)(u < thi) << xb;
                 tie |= (u == thi);
             }
@@ -208,8 +208,6 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     c.rr = (uint32_t)r;
     c.k0 = (uint32_t)st->seed;
     c.k1 = (uint32_t)(st->seed >> 32);
-    c.d5 = (int)th.thi5 - (int)th.thi4;
-    c.d6 = (int)th.thi6 - (int)th.thi4;
 
     // this lane's planes z = j PL .. j PL + PL - 1 into LDS (plane loops here and in the write-back
     // stay rolled: unrolled, their 64-bit row addresses are shared between the two and held live
