@@ -249,3 +249,44 @@ def run(dim, L, J, seed, R0, betas, ns, capacity=None, R_targets=None):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def bootstrap(x, idx, A=None, R=None):
+    """Bootstrap errors of the weighted averages (Sec. III: the error is the standard deviation
+    over resampled ensembles of size M).  idx [n_boot][M]: run indices drawn with replacement,
+    one resampled ensemble per row.  Returns (replicates [n_boot][n_obs + 3], errors [n_obs + 3]):
+    each replicate row is (A_bar[0..n_obs-1], -beta F_bar, Var, mean) of weighted_average on the
+    resampled runs; errors are the standard deviations over the rows (1 / (n_boot - 1))."""
+    x = np.asarray(x, np.float64)
+    M = len(x)
+    A = np.zeros((M, 0)) if A is None else np.asarray(A, np.float64).reshape(M, -1)
+    idx = np.asarray(idx, np.int64)
+    reps = []
+    for row in idx:
+        w = weighted_average(x[row], A[row], None if R is None else np.asarray(R, np.float64)[row])
+        reps.append(np.concatenate([w["A_bar"], [w["minus_betaF_bar"], w["var"], w["mean"]]]))
+    reps = np.array(reps)
+    n = len(reps)
+    mean = reps.sum(axis=0) / n
+    err = np.sqrt(((reps - mean) ** 2).sum(axis=0) / (n - 1)) if n > 1 else np.zeros(reps.shape[1])
+    return reps, err
+
+
+def ring_exact(J, beta):
+    """ln Z and the mean energy of the periodic +-J chain with E = + sum_i J_i s_i s_(i+1) (the sign
+    of Sec. IV), from the 2 x 2 transfer matrices T_i = [[e^(-b J_i), e^(b J_i)], [e^(b J_i),
+    e^(-b J_i)]]: Z = trace of their product, E = -d ln Z / d beta by the product rule (each
+    factor rescaled by its largest entry to keep the product finite)."""
+    J = np.asarray(J, np.float64)
+    P = np.eye(2)
+    dP = np.zeros((2, 2))
+    lnc = 0.0
+    for j in J:
+        T = np.array([[np.exp(-beta * j), np.exp(beta * j)], [np.exp(beta * j), np.exp(-beta * j)]])
+        dT = np.array([[-j * np.exp(-beta * j), j * np.exp(beta * j)], [j * np.exp(beta * j), -j * np.exp(-beta * j)]])
+        c = np.abs(T).max()
+        dP = dP @ (T / c) + P @ (dT / c)
+        P = P @ (T / c)
+        lnc += np.log(c)
+    Z = np.trace(P)
+    return lnc + np.log(Z), -np.trace(dP) / Z
