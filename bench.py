@@ -51,9 +51,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
-                        "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12")
+                        "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
+                        "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs)")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
@@ -186,6 +187,33 @@ def sweep_traffic(path):
     return tr.get("bytes_per_launch")
 
 
+def bench_bias(args):
+    """Sec. IV's 1D bias measurement on the ±J ring (N = 64, R0 = 1000, 51 temperatures, 5 sweeps):
+    18 realizations x 200 runs; weighted and plain energy and free energy at beta = 5 against the
+    exact chain, bootstrap errors, and the block bias mu_k.  value = mean weighted energy bias."""
+    from paper_1006_0252_amd import bias
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    r = bias.run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), log=log)
+    res = r["by_beta"]
+    fb = res[5.0]["free_energy_bias_weighted"]
+    out = {
+        "metric": METRIC, "value": fb[0], "unit": "weighted -beta F_bar minus exact at beta=5, mean over realizations",
+        "n_gpus": 1, "steps": 18 * 50, "warmup": 0, "ms_per_step": r["anneal_seconds"] / (18 * 50) * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8+f64", "data": "synthetic",
+        "config": {"workload": "ring_N64_bias_18x200", "N": 64, "R0": 1000, "n_temps": 51, "n_sweeps": 5,
+                   "realizations": 18, "runs_per_realization": 200, "bootstrap_replicates": 100},
+        "by_beta": {str(b): {"energy_bias": {"weighted": list(v["energy_bias_weighted"]),
+                                             "plain": list(v["energy_bias_plain"])},
+                             "free_energy_bias": {"weighted": list(v["free_energy_bias_weighted"]),
+                                                  "plain": list(v["free_energy_bias_plain"])},
+                             "mean_var_betaF": v["mean_var"], "mu_k": {str(k): m for k, m in v["mu_k"].items()}}
+                    for b, v in res.items()},
+        "anneal_attempts_per_s": r["attempts"] / r["anneal_seconds"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -225,6 +253,9 @@ def main():
         return
     if args.workload == "learned":
         bench_learned(args)
+        return
+    if args.workload == "bias":
+        bench_bias(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1

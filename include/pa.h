@@ -244,6 +244,17 @@ int pa_weighted_average(int M, const double* minus_betaF, const double* R, const
 int pa_weighted_average_dev(int n_sets, int M, const double* minus_betaF, const double* R, const double* A,
                             int n_obs, double* out, void* stream);
 
+/* Bootstrap errors of the device weighted averages (Sec. III: the error is the standard
+ * deviation over resampled ensembles, each of M runs).  idx is device int32 [n_boot][M]: run
+ * indices in [0, M) drawn by the caller with replacement, one resampled ensemble per row, the
+ * same rows for every set.  rep (device [n_sets][n_boot][n_obs + 3]) receives each resampled
+ * ensemble's (A_bar, -beta F_bar, var, mean) as pa_weighted_average_dev computes them; err
+ * (device [n_sets][n_obs + 3]) their standard deviations over the n_boot rows (1/(n_boot - 1)).
+ * A row holding an index outside [0, M) gives NaN for that replicate (and so for err).
+ * The other arguments are those of pa_weighted_average_dev. */
+int pa_bootstrap_dev(int n_sets, int M, const double* minus_betaF, const double* R, const double* A, int n_obs,
+                     int n_boot, const int32_t* idx, double* rep, double* err, void* stream);
+
 /* Synchronise each run's stream and read its sticky status bits into host_flags[r];
  * returns PA_OK, or the PA_ERR_* code of the first raised bit. */
 int pa_status(const pa_run* runs, int n_runs, int32_t* host_flags);

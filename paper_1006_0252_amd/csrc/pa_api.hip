@@ -305,6 +305,14 @@ int pa_weighted_average_dev(int n_sets, int M, const double* x, const double* R,
     return launch_weighted_average_dev(n_sets, M, x, R, A, n_obs, out, (hipStream_t)stream);
 }
 
+int pa_bootstrap_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs, int n_boot,
+                     const int32_t* idx, double* rep, double* err, void* stream)
+{
+    if (n_sets <= 0 || M <= 0 || !x || n_obs < 0 || (n_obs > 0 && !A) || n_boot <= 0 || !idx || !rep || !err)
+        return PA_ERR_ARG;
+    return launch_bootstrap_dev(n_sets, M, x, R, A, n_obs, n_boot, idx, rep, err, (hipStream_t)stream);
+}
+
 int pa_status(const pa_run* runs, int n_runs, int32_t* host_flags)
 {
     if (!runs || n_runs <= 0) return PA_ERR_ARG;

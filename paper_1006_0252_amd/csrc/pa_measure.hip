@@ -181,39 +181,52 @@ int launch_free_energy(const pa_run* runs, int n, double* out, hipStream_t s)
     return hip_status(hipGetLastError());
 }
 
-// one thread per set, same arithmetic order as the host version
-__global__ void k_weighted_average(int n_sets, int M, const double* __restrict__ x, const double* __restrict__ R,
-                                   const double* __restrict__ A, int n_obs, double* __restrict__ out)
+// weighted average of one set of M runs (Sec. III), optionally through a row of resampled run
+// indices; same arithmetic order as the host version.  o[0..n_obs-1] = A_bar, o[n_obs] =
+// -beta F_bar, o[n_obs+1] = Var, o[n_obs+2] = mean.
+__device__ void weighted_one(int M, const double* __restrict__ xs, const double* __restrict__ Rs,
+                             const double* __restrict__ As, int n_obs, const int32_t* __restrict__ pick,
+                             double* __restrict__ o)
 {
-    const int set = blockIdx.x * blockDim.x + threadIdx.x;
-    if (set >= n_sets) return;
-    const double* xs = x + (int64_t)set * M;
-    const double* Rs = R ? R + (int64_t)set * M : nullptr;
-    const double* As = A + (int64_t)set * M * n_obs;
-    double* o = out + (int64_t)set * (n_obs + 3);
     double xmax = -INFINITY;
-    for (int r = 0; r < M; ++r) {
+    for (int i = 0; i < M; ++i) {
+        const int r = pick ? pick[i] : i;
         const double xr = xs[r] + (Rs ? log(Rs[r]) : 0.0);
         if (xr > xmax) xmax = xr;
     }
     double Z = 0.0, Rsum = 0.0;
-    for (int r = 0; r < M; ++r) {
+    for (int i = 0; i < M; ++i) {
+        const int r = pick ? pick[i] : i;
         Z += exp(xs[r] + (Rs ? log(Rs[r]) : 0.0) - xmax);
         Rsum += Rs ? Rs[r] : 1.0;
     }
     for (int k = 0; k < n_obs; ++k) o[k] = 0.0;
-    for (int r = 0; r < M; ++r) {
+    for (int i = 0; i < M; ++i) {
+        const int r = pick ? pick[i] : i;
         const double w = exp(xs[r] + (Rs ? log(Rs[r]) : 0.0) - xmax) / Z;
         for (int k = 0; k < n_obs; ++k) o[k] += w * As[(int64_t)r * n_obs + k];
     }
     o[n_obs] = xmax + log(Z) - log(Rsum);
     double m = 0.0;
-    for (int r = 0; r < M; ++r) m += xs[r];
+    for (int i = 0; i < M; ++i) m += xs[pick ? pick[i] : i];
     m /= (double)M;
     double v = 0.0;
-    for (int r = 0; r < M; ++r) v += (xs[r] - m) * (xs[r] - m);
+    for (int i = 0; i < M; ++i) {
+        const double d = xs[pick ? pick[i] : i] - m;
+        v += d * d;
+    }
     o[n_obs + 1] = M > 1 ? v / (double)(M - 1) : 0.0;
     o[n_obs + 2] = m;
+}
+
+// one thread per set
+__global__ void k_weighted_average(int n_sets, int M, const double* __restrict__ x, const double* __restrict__ R,
+                                   const double* __restrict__ A, int n_obs, double* __restrict__ out)
+{
+    const int set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets) return;
+    weighted_one(M, x + (int64_t)set * M, R ? R + (int64_t)set * M : nullptr, A + (int64_t)set * M * n_obs, n_obs,
+                 nullptr, out + (int64_t)set * (n_obs + 3));
 }
 
 int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
@@ -221,6 +234,56 @@ int launch_weighted_average_dev(int n_sets, int M, const double* x, const double
 {
     hipLaunchKernelGGL(k_weighted_average, dim3((unsigned)((n_sets + 63) / 64)), dim3(64), 0, s, n_sets, M, x, R, A,
                        n_obs, out);
+    return hip_status(hipGetLastError());
+}
+
+// bootstrap replicates: thread per (set, replicate b), the weighted average of the runs idx[b][.]
+__global__ void k_bootstrap(int n_sets, int M, const double* __restrict__ x, const double* __restrict__ R,
+                            const double* __restrict__ A, int n_obs, int n_boot, const int32_t* __restrict__ idx,
+                            double* __restrict__ rep)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_sets * n_boot) return;
+    const int set = (int)(t / n_boot), b = (int)(t % n_boot);
+    const int32_t* pick = idx + (int64_t)b * M;
+    for (int i = 0; i < M; ++i) {
+        if ((uint32_t)pick[i] >= (uint32_t)M) {  // an index outside the set: no read, NaN results
+            for (int q = 0; q < n_obs + 3; ++q) rep[t * (n_obs + 3) + q] = NAN;
+            return;
+        }
+    }
+    weighted_one(M, x + (int64_t)set * M, R ? R + (int64_t)set * M : nullptr, A + (int64_t)set * M * n_obs, n_obs,
+                 pick, rep + t * (n_obs + 3));
+}
+
+// error of each quantity: standard deviation over the replicates (1 / (n_boot - 1)), in order
+__global__ void k_bootstrap_err(int n_sets, int n_obs, int n_boot, const double* __restrict__ rep,
+                                double* __restrict__ err)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nq = n_obs + 3;
+    if (t >= (int64_t)n_sets * nq) return;
+    const int set = (int)(t / nq), q = (int)(t % nq);
+    const double* r = rep + (int64_t)set * n_boot * nq + q;
+    double m = 0.0;
+    for (int b = 0; b < n_boot; ++b) m += r[(int64_t)b * nq];
+    m /= (double)n_boot;
+    double v = 0.0;
+    for (int b = 0; b < n_boot; ++b) {
+        const double d = r[(int64_t)b * nq] - m;
+        v += d * d;
+    }
+    err[t] = n_boot > 1 ? sqrt(v / (double)(n_boot - 1)) : 0.0;
+}
+
+int launch_bootstrap_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs, int n_boot,
+                         const int32_t* idx, double* rep, double* err, hipStream_t s)
+{
+    const int64_t nr = (int64_t)n_sets * n_boot, ne = (int64_t)n_sets * (n_obs + 3);
+    hipLaunchKernelGGL(k_bootstrap, dim3((unsigned)((nr + 63) / 64)), dim3(64), 0, s, n_sets, M, x, R, A, n_obs, n_boot,
+                       idx, rep);
+    hipLaunchKernelGGL(k_bootstrap_err, dim3((unsigned)((ne + 63) / 64)), dim3(64), 0, s, n_sets, n_obs, n_boot,
+                       (const double*)rep, err);
     return hip_status(hipGetLastError());
 }
 
