@@ -51,10 +51,11 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "stepped"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
                         "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
-                        "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs)")
+                        "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs); "
+                        "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
@@ -214,6 +215,41 @@ def bench_bias(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_stepped(args):
+    """Sec. IV's stepped population size on the L = 8 cube: the worst of 25 realizations at R = 2000
+    (101 temperatures, 10 sweeps), then 200 runs each with constant R, with R_beta stepped x3 at
+    beta = 0.9 at equal work, and with learned schedules (rho* = 0.1, 0.2) at constant R.
+    value = Var(beta F~) at beta = 5, constant over stepped."""
+    from paper_1006_0252_amd import learned, stepped
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    Xt, Dt, Xv, Dv = learned.training_set(device="cuda:0")
+    nets, _ = learned.train_networks(Xt, Dt, targets=learned.RHO_TARGETS, steps=3000, device="cuda:0")
+    r = stepped.run(learned_nets={0.1: nets[0.1], 0.2: nets[0.2]}, log=log)
+
+    def summ(v):
+        b = np.array(v["betas"])
+        return {"var_beta5": v["var"][-1], "attempts": v["attempts"], "var_x_work": v["var"][-1] * v["attempts"],
+                "n_temps": len(b), "seconds": v["seconds"], "minus_betaF_bar": v["minus_betaF_bar"][-1],
+                "var_at": {f"{x:.2f}": v["var"][int(np.argmin(np.abs(b - x)))] for x in (0.5, 0.9, 1.5, 2.5, 3.5, 5.0)}}
+
+    summary = {w: {k: summ(v) for k, v in P.items()} for w, P in r["profiles"].items()}
+    W = summary["worst"]
+    best_step = min((k for k in W if k.startswith("stepped")), key=lambda k: W[k]["var_beta5"])
+    n_steps = sum(v["n_temps"] - 1 for P in summary.values() for v in P.values())
+    out = {
+        "metric": METRIC, "value": W["constant"]["var_beta5"] / W[best_step]["var_beta5"],
+        "unit": "Var(beta F~) at beta=5 on the worst realization, constant R / best stepped R (equal work)",
+        "n_gpus": 1, "steps": n_steps, "warmup": 0,
+        "ms_per_step": sum(v["seconds"] for P in summary.values() for v in P.values()) / n_steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "stepped_R_cube_L8_R2000", "L": 8, "R": 2000, "n_temps": 101, "n_sweeps": 10,
+                   "runs": 200, "beta_c": [0.9, 2.0], "ratio": 3, "realizations": r["picks"]},
+        "schedules": summary, "var_by_realization": r["var_by_realization"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -256,6 +292,9 @@ def main():
         return
     if args.workload == "bias":
         bench_bias(args)
+        return
+    if args.workload == "stepped":
+        bench_stepped(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1
