@@ -74,6 +74,18 @@ def lib():
         L.orc_weighted_average.argtypes = [i32, P, P, P, i32, P, P, P, P, P]
         L.orc_run.argtypes = [i32, i32, P, u64, i64, i32, P, P, i32, i64, P, P, P, P]
         L.orc_num_threads.argtypes = []
+        L.orc_expd.argtypes = [f64]
+        L.orc_expd.restype = f64
+        L.orc_couplings_gauss.argtypes = [i32, i32, u64, P]
+        L.orc_energy_gauss.argtypes = [i32, i32, P, P]
+        L.orc_energy_gauss.restype = f64
+        L.orc_delta_energy_gauss.argtypes = [i32, i32, P, P, i32]
+        L.orc_delta_energy_gauss.restype = f64
+        L.orc_init_range_gauss.argtypes = [i32, i32, P, u64, i64, i64, P, P]
+        L.orc_sweep_range_gauss.argtypes = [i32, i32, P, u64, f64, i64, i64, P, P, i64, i32]
+        L.orc_copy_numbers_gauss.argtypes = [u64, i64, f64, f64, f64, i64, P, P, P]
+        L.orc_energy_moments_gauss.argtypes = [i64, P, P]
+        L.orc_run_gauss.argtypes = [i32, i32, P, u64, i64, i32, P, P, i32, i64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -290,3 +302,72 @@ def ring_exact(J, beta):
         lnc += np.log(c)
     Z = np.trace(P)
     return lnc + np.log(Z), -np.trace(dP) / Z
+
+
+# ------------------------------------------------------------------ Gaussian couplings (Sec. IV)
+
+def expd(x):
+    """exp written out (Cody-Waite reduction, Taylor series to r^13, exact scaling)."""
+    return lib().orc_expd(float(x))
+
+
+def couplings_gauss(dim, L, disorder_seed):
+    J = np.zeros(num_bonds(dim, L), dtype=np.float64)
+    lib().orc_couplings_gauss(dim, L, disorder_seed, _p(J))
+    return J
+
+
+def energy_gauss(dim, L, J, s):
+    return lib().orc_energy_gauss(dim, L, _p(np.ascontiguousarray(J, np.float64)), _p(np.ascontiguousarray(s, np.uint8)))
+
+
+def delta_energy_gauss(dim, L, J, s, i):
+    return lib().orc_delta_energy_gauss(dim, L, _p(np.ascontiguousarray(J, np.float64)),
+                                        _p(np.ascontiguousarray(s, np.uint8)), i)
+
+
+def init_replicas_gauss(dim, L, J, seed, r_first, count):
+    N = num_sites(dim, L)
+    s = np.zeros((count, N), dtype=np.uint8)
+    E = np.zeros(count, dtype=np.float64)
+    lib().orc_init_range_gauss(dim, L, _p(np.ascontiguousarray(J, np.float64)), seed, r_first, count, _p(s), _p(E))
+    return s, E
+
+
+def sweep_replicas_gauss(dim, L, J, seed, beta, r_first, s, E, t0, ns):
+    """In place: ns sweeps of replicas r_first .. r_first + len(s) - 1; energies recomputed after."""
+    assert s.flags.c_contiguous and E.flags.c_contiguous and E.dtype == np.float64
+    lib().orc_sweep_range_gauss(dim, L, _p(np.ascontiguousarray(J, np.float64)), seed, beta, r_first, len(s), _p(s),
+                                _p(E), t0, ns)
+
+
+def copy_numbers_gauss(seed, k, beta_from, beta_to, R_target, E):
+    E = np.ascontiguousarray(E, np.float64)
+    counts = np.zeros(len(E), dtype=np.int32)
+    out = np.zeros(3)
+    st = lib().orc_copy_numbers_gauss(seed, k, beta_from, beta_to, R_target, len(E), _p(E), _p(counts), _p(out))
+    return st, counts, out[0], out[1], out[2]
+
+
+def energy_moments_gauss(E):
+    E = np.ascontiguousarray(E, np.float64)
+    out = np.zeros(3)
+    lib().orc_energy_moments_gauss(len(E), _p(E), _p(out))
+    return out
+
+
+def run_gauss(dim, L, J, seed, R0, betas, ns, capacity=None, R_targets=None):
+    """A whole run with Gaussian couplings; returns (status, rec[nT][8], final spins, final E)."""
+    N = num_sites(dim, L)
+    betas = np.ascontiguousarray(betas, np.float64)
+    nT = len(betas)
+    cap = capacity or int(R0 * 1.5 + 64)
+    rec = np.zeros((nT, REC_W))
+    s = np.zeros((cap, N), dtype=np.uint8)
+    E = np.zeros(cap, dtype=np.float64)
+    R_out = ctypes.c_int64(0)
+    Rt = None if R_targets is None else np.ascontiguousarray(R_targets, np.float64)
+    st = lib().orc_run_gauss(dim, L, _p(np.ascontiguousarray(J, np.float64)), seed, R0, nT, _p(betas), _p(Rt), ns,
+                             cap, _p(rec), _p(s), _p(E), ctypes.byref(R_out))
+    R = R_out.value
+    return st, rec, s[:R], E[:R]

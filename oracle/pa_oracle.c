@@ -625,6 +625,238 @@ int orc_run(int dim, int L, const int8_t* J, uint64_t seed, int64_t R0, int nT, 
     return status;
 }
 
+/* ========================================================================= */
+/* Gaussian couplings (the model of Sec. IV: J_ij independent normal, mean 0,  */
+/* variance 1).  Energies are real, so every floating-point step below is      */
+/* fixed in order and in the operations used, and the library follows the    */
+/* same definitions with its own code:                                         */
+/*   J_b: Box-Muller from Philox(ctr = (b, 0, 0, 6), key = disorder seed):     */
+/*        m1 = (w0 >> 5) 2^26 + (w1 >> 6), u1 = (m1 + 1) 2^-53 in (0, 1],     */
+/*        m2 = (w2 >> 5) 2^26 + (w3 >> 6), u2 = m2 2^-53 in [0, 1),            */
+/*        J_b = sqrt(-2 ln u1) cos(2 pi u2)            (libm, host side);      */
+/*   E  = sum over bonds b = 0, 1, ... of J_b s_i s_j, added in bond order     */
+/*        starting from 0, recomputed after every call of ns sweeps;           */
+/*   h_i = sum over the incident bonds in the order +x, +y, +z, -x, -y, -z     */
+/*        (chain: +1, -1) of J s_other; dE = -2 s_i h_i;                       */
+/*   accept dE <= 0; otherwise p = expd(-(beta dE)); accept if p >= 1, else    */
+/*        with T64 = (uint64) (p 2^64) by the lazy 16 + 48-bit compare;        */
+/*   resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))),              */
+/*        S = sum over blocks of 256 consecutive replicas (in order) of the     */
+/*        block's sum (in order), ln Q = -dbeta E_lo + ln S - ln R~,           */
+/*        copies of j ~ Poisson((R_target w_j) / S) as for +-J couplings.      */
+/* expd is exp written out: x = k ln 2 + r with k = floor(x / ln 2 + 1/2), r   */
+/* by a two-part ln 2 (Cody and Waite), e^r by its Taylor series to r^13 in    */
+/* Horner form, then scaled by 2^k; 0 for x < -745.                            */
+/* ========================================================================= */
+#define TAG_GAUSS 6u
+
+double orc_expd(double x)
+{
+    static const double c[14] = {1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333,
+                                 0.001388888888888889, 0.0001984126984126984, 2.48015873015873e-05,
+                                 2.7557319223985893e-06, 2.755731922398589e-07, 2.505210838544172e-08,
+                                 2.08767569878681e-09, 1.6059043836821613e-10};
+    const double inv_ln2 = 1.4426950408889634;
+    const double ln2_hi = 0.6931471803691238;     /* 32 significant bits: k ln2_hi is exact */
+    const double ln2_lo = 1.9082149292705877e-10; /* ln 2 - ln2_hi */
+    if (x < -745.0) return 0.0;
+    double k = floor(x * inv_ln2 + 0.5);
+    double r = (x - k * ln2_hi) - k * ln2_lo;
+    double p = c[13];
+    for (int n = 12; n >= 0; --n) p = p * r + c[n];
+    return ldexp(p, (int)k);
+}
+
+void orc_couplings_gauss(int dim, int L, uint64_t disorder_seed, double* J)
+{
+    int nb = orc_num_bonds(dim, L);
+    for (int b = 0; b < nb; ++b) {
+        uint32_t w[4];
+        philox_seeded((uint32_t)b, 0, 0, TAG_GAUSS, disorder_seed, w);
+        uint64_t m1 = ((uint64_t)(w[0] >> 5) << 26) | (uint64_t)(w[1] >> 6);
+        uint64_t m2 = ((uint64_t)(w[2] >> 5) << 26) | (uint64_t)(w[3] >> 6);
+        double u1 = ldexp((double)(m1 + 1), -53);
+        double u2 = ldexp((double)m2, -53);
+        J[b] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+double orc_energy_gauss(int dim, int L, const double* J, const uint8_t* s)
+{
+    int nb = orc_num_bonds(dim, L);
+    double E = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        int i, j;
+        bond_ends(dim, L, b, &i, &j);
+        double t = spin_value(s[i]) * spin_value(s[j]) > 0 ? J[b] : -J[b];
+        E = E + t;
+    }
+    return E;
+}
+
+double orc_delta_energy_gauss(int dim, int L, const double* J, const uint8_t* s, int i)
+{
+    double h = 0.0;
+    for (int k = 0; k < coordination(dim); ++k) {
+        int b, j;
+        incident_bond(dim, L, i, k, &b, &j);
+        h = h + (spin_value(s[j]) > 0 ? J[b] : -J[b]);
+    }
+    return spin_value(s[i]) > 0 ? -2.0 * h : 2.0 * h;
+}
+
+void orc_init_range_gauss(int dim, int L, const double* J, uint64_t seed, int64_t r_first, int64_t count,
+                          uint8_t* s, double* E)
+{
+    int N = orc_num_sites(dim, L);
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t r = r_first + q;
+        for (int i = 0; i < N; ++i) {
+            uint32_t out[4];
+            philox_seeded((uint32_t)(i >> 7), (uint32_t)r, 0, TAG_INIT, seed, out);
+            s[q * N + i] = (uint8_t)((out[(i & 127) >> 5] >> (i & 31)) & 1);
+        }
+        E[q] = orc_energy_gauss(dim, L, J, s + q * N);
+    }
+}
+
+/* acceptance of a move with energy change dE > 0 at beta (the same 64-bit rule as for +-J) */
+static int accept_gauss(uint64_t seed, int64_t r, int64_t t, int colour, int i, double beta, double dE)
+{
+    if (dE <= 0.0) return 1;
+    double p = orc_expd(-(beta * dE));
+    if (p >= 1.0) return 1;
+    uint64_t T64 = (uint64_t)ldexp(p, 64);
+    return orc_met_accept(seed, r, t, colour, i, T64);
+}
+
+void orc_sweep_range_gauss(int dim, int L, const double* J, uint64_t seed, double beta, int64_t r_first,
+                           int64_t count, uint8_t* spins, double* E, int64_t t0, int ns)
+{
+    int N = orc_num_sites(dim, L);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t r = r_first + q;
+        uint8_t* s = spins + q * N;
+        for (int64_t t = t0; t < t0 + ns; ++t)
+            for (int colour = 0; colour < 2; ++colour)
+                for (int i = 0; i < N; ++i) {
+                    if (orc_colour(dim, L, i) != colour) continue;
+                    double dE = orc_delta_energy_gauss(dim, L, J, s, i);
+                    if (accept_gauss(seed, r, t, colour, i, beta, dE)) s[i] ^= 1;
+                }
+        if (ns > 0) E[q] = orc_energy_gauss(dim, L, J, s);
+    }
+}
+
+/* copy numbers of one resampling step; out[0] = S, out[1] = ln Q, out[2] = E_lo */
+int orc_copy_numbers_gauss(uint64_t seed, int64_t k, double beta_from, double beta_to, double R_target, int64_t R,
+                           const double* E, int32_t* counts, double* out)
+{
+    double dbeta = beta_to - beta_from;
+    if (R <= 0 || !(dbeta >= 0.0) || !(R_target > 0.0)) return ORC_ERR_ARG;
+    double E_lo = E[0];
+    for (int64_t j = 1; j < R; ++j)
+        if (E[j] < E_lo) E_lo = E[j];
+    double S = 0.0;
+    for (int64_t b0 = 0; b0 < R; b0 += 256) {
+        double part = 0.0;
+        for (int64_t j = b0; j < R && j < b0 + 256; ++j) part = part + orc_expd(-(dbeta * (E[j] - E_lo)));
+        S = S + part;
+    }
+    out[0] = S;
+    out[1] = -dbeta * E_lo + log(S) - log((double)R);
+    out[2] = E_lo;
+    if (!isfinite(S) || !(S > 0.0)) return ORC_ERR_NONFINITE;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < R; ++j) {
+        double w = orc_expd(-(dbeta * (E[j] - E_lo)));
+        counts[j] = (int32_t)orc_poisson((R_target * w) / S, seed, j, k);
+    }
+    return ORC_OK;
+}
+
+void orc_energy_moments_gauss(int64_t R, const double* E, double* out)
+{
+    double sum = 0.0;
+    for (int64_t j = 0; j < R; ++j) sum += E[j];
+    double mean = sum / (double)R;
+    double m2 = 0.0, m3 = 0.0;
+    for (int64_t j = 0; j < R; ++j) {
+        double d = E[j] - mean;
+        m2 += d * d;
+        m3 += d * d * d;
+    }
+    m2 /= (double)R;
+    m3 /= (double)R;
+    out[0] = mean;
+    out[1] = m2;
+    out[2] = m2 > 0.0 ? m3 / (m2 * sqrt(m2)) : 0.0;
+}
+
+/* a whole run with Gaussian couplings; rec as for orc_run */
+int orc_run_gauss(int dim, int L, const double* J, uint64_t seed, int64_t R0, int nT, const double* betas,
+                  const double* R_targets, int ns, int64_t cap, double* rec, uint8_t* spins_out, double* E_out,
+                  int64_t* R_out)
+{
+    int N = orc_num_sites(dim, L);
+    uint8_t* s[2];
+    double* E[2];
+    s[0] = (uint8_t*)malloc((size_t)cap * N);
+    s[1] = (uint8_t*)malloc((size_t)cap * N);
+    E[0] = (double*)malloc((size_t)cap * sizeof(double));
+    E[1] = (double*)malloc((size_t)cap * sizeof(double));
+    int32_t* counts = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    int status = ORC_OK;
+    int cur = 0;
+    int64_t R = R0;
+    double acc = 0.0, lnOmega = (double)N * log(2.0);
+    if (R0 > cap) status = ORC_ERR_CAPACITY;
+    else orc_init_range_gauss(dim, L, J, seed, 0, R0, s[0], E[0]);
+    for (int k = 0; k < nT; ++k) {
+        double* rk = rec + (int64_t)k * REC_W;
+        rk[2] = 0.0;
+        if (status == ORC_OK && k > 0) {
+            double out[3];
+            double Rt = R_targets ? R_targets[k] : (double)R0;
+            status = orc_copy_numbers_gauss(seed, k, betas[k - 1], betas[k], Rt, R, E[cur], counts, out);
+            if (status == ORC_OK) {
+                int64_t tot = 0;
+                for (int64_t j = 0; j < R; ++j) tot += counts[j];
+                if (tot > cap) status = ORC_ERR_CAPACITY;
+                else if (tot == 0) status = ORC_ERR_EXTINCT;
+            }
+            if (status == ORC_OK) {
+                int64_t dst = 0;
+                for (int64_t j = 0; j < R; ++j)
+                    for (int32_t c = 0; c < counts[j]; ++c, ++dst) {
+                        memcpy(s[cur ^ 1] + dst * N, s[cur] + j * N, (size_t)N);
+                        E[cur ^ 1][dst] = E[cur][j];
+                    }
+                acc += out[1];
+                cur ^= 1;
+                R = dst;
+                orc_sweep_range_gauss(dim, L, J, seed, betas[k], 0, R, s[cur], E[cur], (int64_t)(k - 1) * ns, ns);
+                rk[2] = out[1];
+            }
+        }
+        double mom[3] = {0, 0, 0};
+        if (status == ORC_OK) orc_energy_moments_gauss(R, E[cur], mom);
+        rk[0] = betas[k];
+        rk[1] = (double)R;
+        rk[3] = lnOmega + acc;
+        rk[4] = mom[0];
+        rk[5] = mom[1];
+        rk[6] = mom[2];
+        rk[7] = (double)status;
+    }
+    if (spins_out) memcpy(spins_out, s[cur], (size_t)R * N);
+    if (E_out) memcpy(E_out, E[cur], (size_t)R * sizeof(double));
+    if (R_out) *R_out = R;
+    free(s[0]); free(s[1]); free(E[0]); free(E[1]); free(counts);
+    return status;
+}
+
 /* number of OpenMP threads the oracle's parallel loops use */
 int orc_num_threads(void)
 {
