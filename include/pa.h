@@ -75,6 +75,10 @@ extern "C" {
 #define PA_U8 0
 #define PA_BITS64 1 /* bit-packed rows, groups of 64 replicas (see above) */
 
+/* coupling kinds */
+#define PA_PM1 0   /* J = +-1 equiprobable (int8 couplings, int32 energies) */
+#define PA_GAUSS 1 /* J normal, mean 0, variance 1 (the model of Sec. IV; FP64 couplings and energies) */
+
 /* Per-temperature record, one per schedule index k, written on the device.
  * pa_resample fills beta .. E_lo of record[k]; pa_measure fills the rest. */
 typedef struct pa_record {
@@ -124,7 +128,8 @@ typedef struct pa_state {
     double beta;    /* current inverse temperature */
     uint32_t work_counter; /* work items taken by a batched sweep (counted in the first run of each group of equal-L runs) */
     uint32_t reserved0;
-    uint8_t pad[40];
+    int32_t couplings;     /* PA_PM1 or PA_GAUSS */
+    uint8_t pad[36];
 } pa_state;
 
 /* Host descriptor of one run; every pointer but stream is a device pointer. */
@@ -133,6 +138,8 @@ typedef struct pa_run {
     int32_t L;               /* linear size (even); N = L or L^3 */
     int32_t layout;          /* PA_U8 or PA_BITS64 */
     int32_t n_records;       /* entries of record[] (schedule length) */
+    int32_t couplings;       /* PA_PM1 or PA_GAUSS (PA_GAUSS: layout PA_U8 only) */
+    int32_t reserved;        /* 0 */
     int64_t capacity;        /* replicas each population buffer holds; multiple of 64 */
     int64_t R0;              /* initial population size and default target size */
     uint64_t seed;           /* run seed */
@@ -174,9 +181,12 @@ typedef struct pa_info {
     double acc, ln_omega, beta;
 } pa_info;
 
-/* Sizes of every buffer of a run.  Returns PA_ERR_ARG for dim not in {1, 3}, odd or
- * too small L (1D: L >= 4; 3D: L >= 2, L <= 32), capacity not a positive multiple of 64. */
-int pa_buffer_sizes(int dim, int L, int layout, int64_t capacity, int n_records, pa_sizes* out);
+/* Buffer sizes (bytes) of one run.  Returns PA_ERR_ARG for dim not in {1, 3}, odd or
+ * too small L (1D: L >= 4; 3D: L >= 2, L <= 32), capacity not a positive multiple of 64, a
+ * coupling kind other than PA_PM1 / PA_GAUSS, or Gaussian couplings with a layout other than
+ * PA_U8.  Couplings take 1 byte per bond (PA_PM1) or 8 (PA_GAUSS), energies 4 or 8 bytes per
+ * replica. */
+int pa_buffer_sizes(int dim, int L, int layout, int couplings, int64_t capacity, int n_records, pa_sizes* out);
 
 /* Initialise runs (Sec. II: R0 replicas at beta = 0, each uniform over the 2^N states):
  *   couplings: J_b = -1 iff bit (b mod 128) of Philox(ctr (b/128, 0, 0, 5), key disorder_seed)
@@ -187,6 +197,23 @@ int pa_buffer_sizes(int dim, int L, int layout, int64_t capacity, int n_records,
  * J_host may be NULL (all runs from their disorder seed) or an array of n_runs host
  * pointers, each NULL or a coupling array.  R0 must not exceed capacity. */
 int pa_init_couplings(pa_run* runs, int n_runs, const int8_t* const* J_host);
+/* Gaussian couplings (runs with couplings = PA_GAUSS, the model of Sec. IV).  The couplings are
+ * drawn on the host and copied to the device before the call returns (J_host must be NULL):
+ *   J_b = sqrt(-2 ln u1) cos(2 pi u2), u1 = (m1 + 1) 2^-53, u2 = m2 2^-53, with
+ *   m1 = (w0 >> 5) 2^26 + (w1 >> 6), m2 = (w2 >> 5) 2^26 + (w3 >> 6) and (w0..w3) =
+ *   Philox(ctr (b, 0, 0, 6), key disorder_seed); libm log, cos and sqrt.
+ * Energies are FP64: E = sum over bonds b = 0, 1, ... of J_b s_i s_j added in bond order from 0,
+ * recomputed in that order after every pa_sweep.  A flip changes E by dE = -2 s_i h_i with the
+ * local field h_i summed in the order +x, +y, +z, -x, -y, -z (chain: +1, -1); a move with
+ * dE > 0 is accepted with probability T64 / 2^64, T64 = (uint64)(expd(-(beta dE)) 2^64), by the
+ * same draws as for +-1 couplings, where expd is exp evaluated as 2^k e^r, k = floor(x / ln 2 +
+ * 1/2), r = (x - k ln2_hi) - k ln2_lo (ln2_hi = 0.6931471803691238, ln2_lo =
+ * 1.9082149292705877e-10), e^r by its Taylor series to r^13 in Horner form, and 0 below -745.
+ * Resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))), S = sum over consecutive blocks
+ * of 256 replicas (in order) of the blocks' sums (in order), ln Q = -dbeta E_lo + ln S - ln R~,
+ * copies of j ~ Poisson((R_target w_j) / S) by the ladder of pa_resample.  FP64 products and
+ * sums are never fused.  Runs with Gaussian couplings are processed one after the other in
+ * calls with n_runs > 1, and pa_resampled_fraction / pa_rho_steps reject them. */
 
 /* theta = step->n_sweeps Metropolis sweeps of every replica at beta = step->beta_to
  * (Sec. II, the equilibration loop of the algorithm).  A sweep updates all sites of

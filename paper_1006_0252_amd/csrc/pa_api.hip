@@ -22,6 +22,8 @@ static int check_run(const pa_run& r)
 {
     if (!geometry_ok(r.dim, r.L)) return PA_ERR_ARG;
     if (r.layout != PA_U8 && r.layout != PA_BITS64) return PA_ERR_ARG;
+    if (r.couplings != PA_PM1 && r.couplings != PA_GAUSS) return PA_ERR_ARG;
+    if (r.couplings == PA_GAUSS && r.layout != PA_U8) return PA_ERR_ARG;
     if (r.capacity <= 0 || r.capacity % 64 != 0 || r.capacity > ((int64_t)1 << 31)) return PA_ERR_ARG;
     if (r.R0 <= 0 || r.R0 > r.capacity || r.n_records <= 0) return PA_ERR_ARG;
     if (!r.J || !r.spins[0] || !r.spins[1] || !r.energy[0] || !r.energy[1] || !r.counts || !r.offsets ||
@@ -37,6 +39,8 @@ static int check_run(const pa_run& r)
 static bool batchable(const pa_run* runs, int n)
 {
     if (n < 2) return false;
+    for (int r = 0; r < n; ++r)
+        if (runs[r].couplings == PA_GAUSS) return false;  // Gaussian runs: one launch per run
     for (int r = 1; r < n; ++r) {
         if (runs[r].state != runs[0].state + r) return false;
         if (runs[r].stream != runs[0].stream || runs[r].layout != runs[0].layout || runs[r].dim != runs[0].dim)
@@ -82,9 +86,11 @@ using namespace pa;
 
 extern "C" {
 
-int pa_buffer_sizes(int dim, int L, int layout, int64_t capacity, int n_records, pa_sizes* out)
+int pa_buffer_sizes(int dim, int L, int layout, int couplings, int64_t capacity, int n_records, pa_sizes* out)
 {
     if (!out || !geometry_ok(dim, L) || (layout != PA_U8 && layout != PA_BITS64)) return PA_ERR_ARG;
+    if (couplings != PA_PM1 && couplings != PA_GAUSS) return PA_ERR_ARG;
+    if (couplings == PA_GAUSS && layout != PA_U8) return PA_ERR_ARG;
     if (capacity <= 0 || capacity % 64 != 0 || n_records <= 0) return PA_ERR_ARG;
     const int64_t N = num_sites(dim, L);
     const int64_t B = num_bonds(dim, L);
@@ -94,12 +100,12 @@ int pa_buffer_sizes(int dim, int L, int layout, int64_t capacity, int n_records,
     out->n_bonds = B;
     out->n_bins = n_bins;
     out->row_stride = stride;
-    out->J_bytes = B;
+    out->J_bytes = couplings == PA_GAUSS ? 8 * B : B;
     // bit-packed: one row word of W bits per replica and lattice row
     const int64_t n_rows = dim == 1 ? (N + 31) / 32 : (int64_t)L * L;
     const int64_t W = dim == 1 ? 32 : (L <= 8 ? 8 : (L <= 16 ? 16 : 32));
     out->spins_bytes = layout == PA_U8 ? capacity * stride : capacity * n_rows * (W / 8);
-    out->energy_bytes = 4 * capacity;
+    out->energy_bytes = (couplings == PA_GAUSS ? 8 : 4) * capacity;
     out->counts_bytes = 4 * capacity;
     out->offsets_bytes = 8 * (capacity + 1);
     out->work_bytes = (int64_t)work_layout(N, n_bins, capacity).total;
@@ -145,7 +151,8 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step)
         return hip_status(hipGetLastError());
     }
     for (int r = 0; r < n_runs; ++r) {
-        st = launch_sweep(runs[r], *step, (hipStream_t)runs[r].stream);
+        if (runs[r].couplings == PA_GAUSS) st = launch_sweep_gauss(runs[r], *step, (hipStream_t)runs[r].stream);
+        else st = launch_sweep(runs[r], *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -160,12 +167,13 @@ int pa_resample(pa_run* runs, int n_runs, const pa_step* step)
         st = check_run(runs[r]);
         if (st != PA_OK) return st;
         pa_sizes sz;
-        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].capacity, runs[r].n_records, &sz);
+        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].couplings, runs[r].capacity, runs[r].n_records, &sz);
         if (step->n_weights < sz.n_bins || step->k >= runs[r].n_records) return PA_ERR_ARG;
     }
     if (batchable(runs, n_runs)) return launch_resample(runs, n_runs, *step, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {
-        st = launch_resample(&runs[r], 1, *step, (hipStream_t)runs[r].stream);
+        if (runs[r].couplings == PA_GAUSS) st = launch_resample_gauss(runs[r], *step, (hipStream_t)runs[r].stream);
+        else st = launch_resample(&runs[r], 1, *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -195,7 +203,8 @@ int pa_measure(pa_run* runs, int n_runs, const int32_t* partner)
     }
     for (int r = 0; r < n_runs; ++r) {
         const pa_run* p = (partner && partner[r] >= 0) ? &runs[partner[r]] : nullptr;
-        int st = launch_measure(&runs[r], 1, p, 0, (hipStream_t)runs[r].stream);
+        int st = runs[r].couplings == PA_GAUSS ? launch_measure_gauss(runs[r], p, (hipStream_t)runs[r].stream)
+                                               : launch_measure(&runs[r], 1, p, 0, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
     return PA_OK;
@@ -244,6 +253,7 @@ static int rho_call(pa_run* runs, int n_runs, const double* args, int n_args, in
     for (int r = 0; r < n_runs; ++r) {
         int st = check_run(runs[r]);
         if (st != PA_OK) return st;
+        if (runs[r].couplings == PA_GAUSS) return PA_ERR_ARG;  // energy histogram needed
     }
     if (batchable(runs, n_runs)) return launch_rho(runs, n_runs, args, n_args, mode, cap, ld, out, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {

@@ -125,4 +125,39 @@ int upload_ladder(hipStream_t s);
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? PA_OK : PA_ERR_HIP; }
 
+// exp written out for the Gaussian-coupling path, so that host and device reach the same bits:
+// x = k ln 2 + r, k = floor(x / ln 2 + 1/2), r by a two-part ln 2 (the high part has 32
+// significant bits, so k ln2_hi is exact), e^r by its Taylor series to r^13 in Horner form,
+// scaled by 2^k; 0 below -745.  Products and sums are rounded one by one.
+__device__ inline double expd(double x)
+{
+#pragma clang fp contract(off)
+    if (x < -745.0) return 0.0;
+    const double k = floor(x * 1.4426950408889634 + 0.5);
+    const double r = (x - k * 0.6931471803691238) - k * 1.9082149292705877e-10;
+    double p = 1.6059043836821613e-10;
+    p = p * r + 2.08767569878681e-09;
+    p = p * r + 2.505210838544172e-08;
+    p = p * r + 2.755731922398589e-07;
+    p = p * r + 2.7557319223985893e-06;
+    p = p * r + 2.48015873015873e-05;
+    p = p * r + 0.0001984126984126984;
+    p = p * r + 0.001388888888888889;
+    p = p * r + 0.008333333333333333;
+    p = p * r + 0.041666666666666664;
+    p = p * r + 0.16666666666666666;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+// Gaussian-coupling path (separate kernels; one run per launch)
+int gauss_couplings_upload(const pa_run& run, hipStream_t s);
+int launch_energy_gauss(const pa_run& run, int buf, int64_t n_replicas, hipStream_t s);
+int launch_sweep_gauss(const pa_run& run, const pa_step& step, hipStream_t s);
+int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s);
+int launch_measure_gauss(const pa_run& run, const pa_run* partner, hipStream_t s);
+int launch_moments_gauss(const pa_run& run, hipStream_t s);
+
 }  // namespace pa

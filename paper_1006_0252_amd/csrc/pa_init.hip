@@ -157,8 +157,10 @@ __global__ void __launch_bounds__(256) k_energy_bits64(const pa_state* __restric
 __global__ void k_init_finish(pa_state* st)
 {
     const int B = st->n_bonds;
-    const int E0 = st->energy[0][0];
-    st->E_base = -B + (((E0 + B) % 4) + 4) % 4;
+    if (st->couplings != PA_GAUSS) {
+        const int E0 = st->energy[0][0];
+        st->E_base = -B + (((E0 + B) % 4) + 4) % 4;
+    }
     for (int k = 0; k < st->n_records; ++k) {
         pa_record* rec = st->record + k;
         double* d = reinterpret_cast<double*>(rec);
@@ -175,7 +177,7 @@ __global__ void k_init_finish(pa_state* st)
 int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s)
 {
     pa_sizes sz;
-    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.capacity, run.n_records, &sz);
+    int rc = pa_buffer_sizes(run.dim, run.L, run.layout, run.couplings, run.capacity, run.n_records, &sz);
     if (rc != PA_OK) return rc;
     pa_state h;
     memset(&h, 0, sizeof(h));
@@ -210,7 +212,22 @@ int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s)
     h.ln_omega = (double)sz.N * log(2.0);
     h.beta = 0.0;
     h.initialised = 0;
+    h.couplings = run.couplings;
     hipLaunchKernelGGL(k_write_state, dim3(1), dim3(1), 0, s, run.state, h);
+
+    const uint32_t s0 = (uint32_t)run.seed, s1 = (uint32_t)(run.seed >> 32);
+    if (run.couplings == PA_GAUSS) {
+        // couplings from the host (libm), then spins as for +-1 couplings and FP64 energies
+        if (J_host) return PA_ERR_ARG;
+        rc = gauss_couplings_upload(run, s);
+        if (rc != PA_OK) return rc;
+        const int64_t threads = run.R0 * (sz.row_stride / 16);
+        hipLaunchKernelGGL(k_init_u8, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.state, s0, s1);
+        rc = launch_energy_gauss(run, 0, run.R0, s);
+        if (rc != PA_OK) return rc;
+        hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(1), 0, s, run.state);
+        return hip_status(hipGetLastError());
+    }
 
     const int B = (int)sz.n_bonds;
     if (J_host) {

@@ -174,6 +174,20 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
     return hip_status(hipGetLastError());
 }
 
+// Gaussian couplings: energy moments from the FP64 energies, overlap as for one byte per spin
+int launch_measure_gauss(const pa_run& run, const pa_run* partner, hipStream_t s)
+{
+    int rc = launch_moments_gauss(run, s);
+    if (rc != PA_OK || !partner) return rc;
+    const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
+    pa_state* base = run.state;
+    hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), 1), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((run.capacity + 3) / 4), 1), dim3(256), 0, s, base,
+                       (const pa_state*)partner->state, 0);
+    hipLaunchKernelGGL(k_overlap_stats, dim3(1, 1), dim3(1), 0, s, base, (const pa_state*)partner->state, 0);
+    return hip_status(hipGetLastError());
+}
+
 int launch_free_energy(const pa_run* runs, int n, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_free_energy, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, (const pa_state*)runs[0].state,

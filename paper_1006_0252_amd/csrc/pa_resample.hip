@@ -390,7 +390,12 @@ __global__ void __launch_bounds__(256) k_gather_u8(pa_state* base)
     const uint4* a = (const uint4*)((const uint8_t*)st->spins[cur] + j * st->row_stride) + c;
     uint4* b = (uint4*)((uint8_t*)st->spins[cur ^ 1] + rn * st->row_stride) + c;
     *b = *a;
-    if (c == 0) st->energy[cur ^ 1][rn] = st->energy[cur][j];
+    if (c == 0) {
+        if (st->couplings == PA_GAUSS)
+            reinterpret_cast<double*>(st->energy[cur ^ 1])[rn] = reinterpret_cast<const double*>(st->energy[cur])[j];
+        else
+            st->energy[cur ^ 1][rn] = st->energy[cur][j];
+    }
 }
 
 // bit-packed gather: lane = destination replica, loop over rows; a row word of replica j sits
@@ -457,7 +462,7 @@ static BatchShape batch_shape(const pa_run* runs, int n)
     BatchShape b;
     for (int r = 0; r < n; ++r) {
         pa_sizes sz;
-        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].capacity, runs[r].n_records, &sz);
+        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].couplings, runs[r].capacity, runs[r].n_records, &sz);
         b.cap_max = std::max(b.cap_max, runs[r].capacity);
         b.bins_max = std::max(b.bins_max, sz.n_bins);
         b.stride_max = std::max(b.stride_max, sz.row_stride);
@@ -501,6 +506,145 @@ int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t 
         hipLaunchKernelGGL(k_gather_bits, dim3(cap_blocks, n), dim3(256), 0, s, base);
     }
     hipLaunchKernelGGL(k_finish, dim3(1, n), dim3(1), 0, s, base, p);
+    return hip_status(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Gaussian couplings
+// Real energies: per-replica weights instead of the energy histogram.  E_lo = min E (exact);
+// w_j = expd(-(dbeta (E_j - E_lo))); S = sum over blocks of 256 consecutive replicas of their
+// in-order sums, added in block order; ln Q = -dbeta E_lo + ln S - ln R~; copies of j ~
+// Poisson((R_target w_j) / S) by the same ladder and draws as the histogram path.
+constexpr int kMiscGaussS = 3;      // misc slot: S (FP64 bits)
+constexpr int kGaussBlock = 256;
+
+__global__ void __launch_bounds__(256) k_gauss_min(pa_state* st)
+{
+    if (st->status) return;
+    __shared__ double red[256];
+    const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
+    double m = INFINITY;
+    for (int64_t j = threadIdx.x; j < st->R; j += blockDim.x) m = fmin(m, E[j]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
+        *reinterpret_cast<double*>(&misc[kMiscEmin]) = red[0];
+    }
+}
+
+// thread per block of 256 replicas: its in-order weight sum, kept in the source-index area
+__global__ void __launch_bounds__(256) k_gauss_blocksum(pa_state* st, double dbeta)
+{
+    if (st->status) return;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t R = st->R;
+    if (b * kGaussBlock >= R) return;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
+    const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
+    double part = 0.0;
+    const int64_t j1 = min(R, (b + 1) * kGaussBlock);
+    for (int64_t j = b * kGaussBlock; j < j1; ++j) part = part + expd(-(dbeta * (E[j] - E_lo)));
+    work_ptr<double>(st, wl.src)[b] = part;
+}
+
+__global__ void k_gauss_normalise(pa_state* st, ResampleParams p)
+{
+    if (st->status) return;
+    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
+    int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const double* part = work_ptr<double>(st, wl.src);
+    const int64_t R = st->R;
+    const int64_t nb = (R + kGaussBlock - 1) / kGaussBlock;
+    double S = 0.0;
+    for (int64_t b = 0; b < nb; ++b) S = S + part[b];
+    const double dbeta = p.beta_to - p.beta_from;
+    const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
+    if (!isfinite(S) || !(S > 0.0)) {
+        st->status |= PA_FLAG_NONFINITE;
+        return;
+    }
+    const double lnQ = -dbeta * E_lo + log(S) - log((double)R);
+    pa_record* rec = st->record + p.k;
+    rec->beta = p.beta_to;
+    rec->lnQ = lnQ;
+    rec->minus_betaF = st->ln_omega + (st->acc + lnQ);
+    rec->S = S;
+    rec->E_lo = E_lo;
+    *reinterpret_cast<double*>(&misc[kMiscLnQ]) = lnQ;
+    *reinterpret_cast<double*>(&misc[kMiscGaussS]) = S;
+}
+
+__global__ void __launch_bounds__(256) k_gauss_copies(pa_state* st, ResampleParams p)
+{
+    if (st->status) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= st->R) return;
+    const int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
+    const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
+    const double S = *reinterpret_cast<const double*>(&misc[kMiscGaussS]);
+    const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
+    const double dbeta = p.beta_to - p.beta_from;
+    const double Rt = p.R_target > 0.0 ? p.R_target : (double)st->R0;
+    const double lam = (Rt * expd(-(dbeta * (E[j] - E_lo)))) / S;
+    int64_t n = 0;
+    if (lam > 0.0) {
+        int64_t q = 0;
+        double rem = lam;
+        if (lam > 64.0) {
+            q = (int64_t)ceil(lam / 64.0) - 1;
+            rem = lam - 64.0 * (double)q;
+        }
+        const int m = ladder_level(rem);
+        const uint64_t keep = (uint64_t)floor(ldexp(rem, 32 - m));
+        const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
+        uint32_t d = 0;
+        uint4v v = {0, 0, 0, 0};
+        auto draw = [&]() -> uint32_t {
+            if ((d & 3) == 0) v = philox10(d >> 2, (uint32_t)j, (uint32_t)p.k, kTagPoisson, k0, k1);
+            const uint32_t u = word_of(v, d & 3);
+            ++d;
+            return u;
+        };
+        for (int64_t blk = 0; blk < q; ++blk) n += invert_ladder(kLadderMax, draw());
+        const int64_t K = invert_ladder(m, draw());
+        for (int64_t e = 0; e < K; ++e)
+            if ((uint64_t)draw() < keep) ++n;
+    }
+    st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
+}
+
+int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s)
+{
+    ResampleParams p;
+    p.beta_from = step.beta_from;
+    p.beta_to = step.beta_to;
+    p.R_target = step.R_target;
+    p.w = nullptr;
+    p.k = step.k;
+    pa_state* st = run.state;
+    const int64_t cap = run.capacity;
+    const unsigned cap_blocks = (unsigned)((cap + 255) / 256);
+    const unsigned n_scan = (unsigned)((cap + kScanTile - 1) / kScanTile);
+    const int64_t n_part = (cap + kGaussBlock - 1) / kGaussBlock;
+    hipLaunchKernelGGL(k_gauss_min, dim3(1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_gauss_blocksum, dim3((unsigned)((n_part + 255) / 256)), dim3(256), 0, s, st,
+                       step.beta_to - step.beta_from);
+    hipLaunchKernelGGL(k_gauss_normalise, dim3(1), dim3(1), 0, s, st, p);
+    hipLaunchKernelGGL(k_gauss_copies, dim3(cap_blocks), dim3(256), 0, s, st, p);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, 1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, 1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_scan_down, dim3(n_scan, 1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_src, dim3(cap_blocks, 1), dim3(256), 0, s, st);
+    const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
+    const int64_t threads = cap * (((N + 15) / 16 * 16) / 16);  // one per 16 bytes of a row
+    hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_finish, dim3(1, 1), dim3(1), 0, s, st, p);
     return hip_status(hipGetLastError());
 }
 

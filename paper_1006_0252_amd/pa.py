@@ -19,6 +19,8 @@ PA_OK, PA_ERR_ARG, PA_ERR_CAPACITY, PA_ERR_EXTINCT, PA_ERR_NONFINITE, PA_ERR_HIP
 PA_FLAG_CAPACITY, PA_FLAG_EXTINCT, PA_FLAG_NONFINITE = 1, 2, 4
 PA_U8, PA_BITS64 = 0, 1
 LAYOUTS = {"u8": PA_U8, "bits64": PA_BITS64}
+PA_PM1, PA_GAUSS = 0, 1
+COUPLINGS = {"pm1": PA_PM1, "gauss": PA_GAUSS}
 
 P = ctypes.c_void_p
 
@@ -35,7 +37,7 @@ RECORD_FIELDS = [f[0] for f in pa_record._fields_][:13]
 class pa_run(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("layout", ctypes.c_int32), ("n_records", ctypes.c_int32),
-        ("capacity", ctypes.c_int64), ("R0", ctypes.c_int64), ("seed", ctypes.c_uint64),
+        ("couplings", ctypes.c_int32), ("reserved", ctypes.c_int32), ("capacity", ctypes.c_int64), ("R0", ctypes.c_int64), ("seed", ctypes.c_uint64),
         ("disorder_seed", ctypes.c_uint64), ("J", P), ("spins", P * 2), ("energy", P * 2), ("counts", P),
         ("offsets", P), ("work", P), ("record", P), ("state", P), ("stream", P),
     ]
@@ -66,7 +68,7 @@ _lib = None
 
 # every entry point declared in include/pa.h, with its ctypes signature
 SIGNATURES = {
-    "pa_buffer_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+    "pa_buffer_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                         ctypes.POINTER(pa_sizes)]),
     "pa_init_couplings": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, P]),
     "pa_sweep": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, ctypes.POINTER(pa_step)]),
@@ -152,9 +154,9 @@ def ladder_table(m, cap=512):
     return C[: n.value].copy()
 
 
-def buffer_sizes(dim, L, layout, capacity, n_records):
+def buffer_sizes(dim, L, layout, capacity, n_records, couplings=0):
     s = pa_sizes()
-    check(lib().pa_buffer_sizes(dim, L, layout, capacity, n_records, ctypes.byref(s)), "pa_buffer_sizes")
+    check(lib().pa_buffer_sizes(dim, L, layout, couplings, capacity, n_records, ctypes.byref(s)), "pa_buffer_sizes")
     return s
 
 
@@ -225,14 +227,15 @@ class Run:
     """One population-annealing run: caller-owned torch buffers described by a pa_run."""
 
     def __init__(self, dim, L, R0, seed, disorder_seed, n_records, capacity=None, layout="u8", device="cuda",
-                 stream=None, state_ptr=None):
+                 stream=None, state_ptr=None, couplings="pm1"):
         import torch
 
         self.dim, self.L, self.R0 = dim, L, int(R0)
         self.layout = LAYOUTS[layout] if isinstance(layout, str) else layout
+        self.couplings_kind = COUPLINGS[couplings] if isinstance(couplings, str) else int(couplings)
         cap = capacity if capacity is not None else int(np.ceil(self.R0 * 1.5 / 64.0)) * 64 + 64
         self.capacity = int(cap)
-        self.sizes = buffer_sizes(dim, L, self.layout, self.capacity, n_records)
+        self.sizes = buffer_sizes(dim, L, self.layout, self.capacity, n_records, self.couplings_kind)
         s = self.sizes
         self.N = int(s.N)
         self.n_bonds = int(s.n_bonds)
@@ -257,6 +260,7 @@ class Run:
             self.stream.wait_stream(alloc_stream)
         r = pa_run()
         r.dim, r.L, r.layout, r.n_records = dim, L, self.layout, n_records
+        r.couplings = self.couplings_kind
         r.capacity, r.R0 = self.capacity, self.R0
         r.seed, r.disorder_seed = int(seed), int(disorder_seed)
         r.J = self.J.data_ptr()
@@ -307,6 +311,8 @@ class Run:
 
     def couplings(self):
         self._sync()
+        if self.couplings_kind == PA_GAUSS:
+            return self.J[: 8 * self.n_bonds].cpu().numpy().view(np.float64).copy()
         return self.J[: self.n_bonds].cpu().numpy().view(np.int8).copy()
 
     def records(self):
@@ -319,13 +325,18 @@ class Run:
         info = self.query()
         R = int(info.R)
         b = info.cur if buf is None else buf
-        E = self.energy[b][: 4 * R].cpu().numpy().view(np.int32).copy()
+        E = self._energy_view(self.energy[b], R)
         raw = self.spins[b].cpu().numpy()
         return unpack_spins(raw, self.dim, self.L, self.layout, R, int(self.sizes.row_stride)), E
 
     def energies(self):
         info = self.query()
-        return self.energy[info.cur][: 4 * int(info.R)].cpu().numpy().view(np.int32).copy()
+        return self._energy_view(self.energy[info.cur], int(info.R))
+
+    def _energy_view(self, buf, R):
+        if self.couplings_kind == PA_GAUSS:
+            return buf[: 8 * R].cpu().numpy().view(np.float64).copy()
+        return buf[: 4 * R].cpu().numpy().view(np.int32).copy()
 
     def replica_spins(self, indices, buf=None):
         """u8 spins [len(indices)][N] of selected replicas of the current population."""
@@ -358,6 +369,7 @@ class Batch:
         for r, sp in enumerate(specs):
             cap = int(np.ceil(sp["R0"] * capacity_factor / 64.0)) * 64 + 64
             self.runs.append(Run(sp["dim"], sp["L"], sp["R0"], sp["seed"], sp["disorder_seed"], n_records,
+                                 couplings=sp.get("couplings", "pm1"),
                                  capacity=cap, layout=layout, device=device, stream=self.stream,
                                  state_ptr=base + 256 * r))
         self.arr = (pa_run * self.n)(*[r.desc for r in self.runs])

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(pa.pa_record) == 128
-    assert ctypes.sizeof(pa.pa_run) == 136
+    assert ctypes.sizeof(pa.pa_run) == 144
     s = pa.buffer_sizes(3, 4, pa.PA_U8, 64, 4)
     assert s.state_bytes == 256 and s.record_bytes == 4 * 128
 
@@ -54,11 +54,19 @@ def test_buffer_sizes(dim, L, layout):
         assert s.spins_bytes == cap * 512  # 0.5 KB per L = 16 replica
 
 
-@pytest.mark.parametrize("args", [(2, 8, 0, 64), (3, 7, 0, 64), (1, 3, 0, 64), (3, 8, 2, 64), (3, 8, 0, 100),
-                                  (3, 8, 0, 0), (3, 34, 0, 64)])
+@pytest.mark.parametrize("args", [(2, 8, 0, 0, 64), (3, 7, 0, 0, 64), (1, 3, 0, 0, 64), (3, 8, 2, 0, 64),
+                                  (3, 8, 0, 0, 100), (3, 8, 0, 0, 0), (3, 34, 0, 0, 64), (3, 8, 0, 2, 64),
+                                  (3, 8, 1, 1, 64)])
 def test_buffer_sizes_rejects(args):
     s = pa.pa_sizes()
     assert pa.lib().pa_buffer_sizes(*args, 4, ctypes.byref(s)) == pa.PA_ERR_ARG
+
+
+def test_buffer_sizes_gaussian():
+    s = pa.buffer_sizes(3, 8, pa.PA_U8, 128, 5, couplings=pa.PA_GAUSS)
+    assert s.J_bytes == 8 * 3 * 512 and s.energy_bytes == 8 * 128
+    p = pa.buffer_sizes(3, 8, pa.PA_U8, 128, 5)
+    assert p.J_bytes == 3 * 512 and p.energy_bytes == 4 * 128 and p.spins_bytes == s.spins_bytes
 
 
 def test_calls_reject_bad_runs_without_touching_the_device():

@@ -1,0 +1,149 @@
+"""Gaussian couplings (the model of Sec. IV) on the GPU against the oracle: couplings, initial
+populations, sweeps, copy numbers and whole runs bit for bit (spins, FP64 energies, copy
+numbers, population sizes); ln Q, -beta F~ and the energy moments within 1e-12."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1006_0252_amd import pa  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def gauss_run(dim, L, R0, seed, ds, n_records=4, capacity=None):
+    return pa.Run(dim, L, R0, seed, ds, n_records, capacity=capacity, layout="u8", device=DEV,
+                  couplings="gauss").init()
+
+
+@pytest.mark.parametrize("dim,L", [(1, 16), (3, 4), (3, 6)])
+def test_couplings_and_initial_population(dim, L):
+    note(f"gauss init dim={dim} L={L}")
+    run = gauss_run(dim, L, 200, 11, 3)
+    J = run.couplings()
+    assert np.array_equal(J, o.couplings_gauss(dim, L, 3))
+    s, E = run.population()
+    s_o, E_o = o.init_replicas_gauss(dim, L, J, 11, 0, 200)
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+
+
+@pytest.mark.parametrize("dim,L,R,beta", [(1, 16, 130, 0.7), (3, 4, 300, 0.7), (3, 4, 77, 3.0), (3, 6, 65, 0.0)])
+def test_sweep_matches_oracle(dim, L, R, beta):
+    note(f"gauss sweep dim={dim} L={L} R={R} beta={beta}")
+    run = gauss_run(dim, L, R, 5, 9)
+    sched = pa.Schedule([0.0, beta], 3, run.n_bins, device=DEV)
+    st = sched.step(1)
+    run.sweep(st)
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    s, E = run.population()
+    J = o.couplings_gauss(dim, L, 9)
+    s_o, E_o = o.init_replicas_gauss(dim, L, J, 5, 0, R)
+    o.sweep_replicas_gauss(dim, L, J, 5, beta, 0, s_o, E_o, 0, 3)
+    assert np.array_equal(s, s_o), np.nonzero((s != s_o).any(axis=1))[0][:10]
+    assert np.array_equal(E, E_o)
+
+
+def test_copy_numbers_match_oracle():
+    note("gauss resample")
+    R = 700
+    run = gauss_run(3, 4, R, 8, 2, capacity=1536)
+    run.sweep(pa.Schedule([0.0, 0.3], 2, run.n_bins, device=DEV).step(1))
+    run.resample(pa.Schedule([0.3, 1.1], 2, run.n_bins, device=DEV).step(1))
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    J = o.couplings_gauss(3, 4, 2)
+    s_o, E_o = o.init_replicas_gauss(3, 4, J, 8, 0, R)
+    o.sweep_replicas_gauss(3, 4, J, 8, 0.3, 0, s_o, E_o, 0, 2)
+    st, counts_o, S_o, lnQ_o, E_lo_o = o.copy_numbers_gauss(8, 1, 0.3, 1.1, float(R), E_o)
+    assert st == 0
+    c, _ = run.counts_offsets(R)
+    assert np.array_equal(c, counts_o)
+    rec = run.records()[1]
+    assert rec[3] == S_o and rec[5] == E_lo_o and rec[4] == counts_o.sum()
+    assert abs(rec[1] - lnQ_o) <= 1e-12 * max(1.0, abs(lnQ_o))
+    s, E = run.population()
+    keep = np.repeat(np.arange(R), counts_o)
+    assert np.array_equal(s, s_o[keep]) and np.array_equal(E, E_o[keep])
+
+
+@pytest.mark.parametrize("dim,L,R0,nT", [(3, 4, 200, 7), (1, 32, 300, 9)])
+def test_whole_run_matches_oracle(dim, L, R0, nT):
+    note(f"gauss run dim={dim} L={L} R0={R0}")
+    betas = [2.5 * k / (nT - 1) for k in range(nT)]
+    ns = 3
+    cap = int(np.ceil(R0 * 1.6 / 64)) * 64
+    run = gauss_run(dim, L, R0, 21, 4, n_records=nT, capacity=cap)
+    sched = pa.Schedule(betas, ns, run.n_bins, device=DEV)
+    for k in range(1, nT):
+        st = sched.step(k)
+        run.resample(st)
+        run.sweep(st)
+        pa.measure([run])
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    J = o.couplings_gauss(dim, L, 4)
+    st_o, rec_o, s_o, E_o = o.run_gauss(dim, L, J, 21, R0, betas, ns, capacity=cap)
+    assert st_o == 0
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+    rec = run.records()
+    assert np.array_equal(rec[:, 4], rec_o[:, 1])
+    for k in range(nT):
+        assert abs(rec[k, 1] - rec_o[k, 2]) <= 1e-12 * max(1.0, abs(rec_o[k, 2])), k
+        assert abs(rec[k, 2] - rec_o[k, 3]) <= 1e-12 * max(1.0, abs(rec_o[k, 3])), k
+        if k > 0:
+            # FP64 sums over the population in another order: rounding only
+            assert abs(rec[k, 6] - rec_o[k, 4]) <= 1e-12 * max(1.0, abs(rec_o[k, 4])), k
+            assert abs(rec[k, 7] - rec_o[k, 5]) <= 1e-12 * max(1.0, abs(rec_o[k, 5])), k
+            assert abs(rec[k, 8] - rec_o[k, 6]) <= 1e-9 * max(1.0, abs(rec_o[k, 6])), k
+    fe = torch.zeros(1, dtype=torch.float64, device=DEV)
+    run.free_energy(fe)
+    assert abs(fe.item() - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
+
+
+def test_overlap_of_gaussian_pair():
+    note("gauss overlap pair")
+    RA, RB = 150, 170
+    a = gauss_run(3, 4, RA, 31, 6)
+    b = gauss_run(3, 4, RB, 32, 6)
+    sched = pa.Schedule([0.0, 1.5], 2, a.n_bins, device=DEV)
+    for r in (a, b):
+        r.sweep(sched.step(1))
+    pa.measure([a, b], [1, 0])
+    J = o.couplings_gauss(3, 4, 6)
+    pops = []
+    for seed, R in ((31, RA), (32, RB)):
+        s_o, E_o = o.init_replicas_gauss(3, 4, J, seed, 0, R)
+        o.sweep_replicas_gauss(3, 4, J, seed, 1.5, 0, s_o, E_o, 0, 2)
+        pops.append(s_o)
+    h, P = o.overlap_hist(64, pops[0], pops[1])
+    q2, q4, g = o.overlap_stats(64, h)
+    for run in (a, b):
+        rec = run.records()[0]
+        assert rec[12] == P
+        for got, want in zip(rec[9:12], (q2, q4, g)):
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
+
+
+def test_gaussian_rejected_where_unsupported():
+    r = pa.pa_sizes()
+    assert pa.lib().pa_buffer_sizes(3, 4, pa.PA_BITS64, pa.PA_GAUSS, 64, 4, ctypes.byref(r)) == pa.PA_ERR_ARG
+    run = gauss_run(3, 4, 64, 1, 1)
+    t = np.array([0.2])
+    out = torch.zeros(1, dtype=torch.float64, device=DEV)
+    assert pa.lib().pa_rho_steps(ctypes.byref(run.desc), 1, pa._np(t), 1, 1.0, 1, out.data_ptr()) == pa.PA_ERR_ARG
