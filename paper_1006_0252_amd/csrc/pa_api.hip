@@ -108,7 +108,7 @@ int pa_buffer_sizes(int dim, int L, int layout, int couplings, int64_t capacity,
     out->energy_bytes = (couplings == PA_GAUSS ? 8 : 4) * capacity;
     out->counts_bytes = 4 * capacity;
     out->offsets_bytes = 8 * (capacity + 1);
-    out->work_bytes = (int64_t)work_layout(N, n_bins, capacity).total;
+    out->work_bytes = (int64_t)(work_layout(N, n_bins, capacity).total + (couplings == PA_GAUSS ? gauss_table_bytes(N) : 0));
     out->record_bytes = (int64_t)sizeof(pa_record) * n_records;
     out->state_bytes = (int64_t)sizeof(pa_state);
     return PA_OK;
@@ -150,8 +150,14 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step)
         if (st != PA_OK) return st;
         return hip_status(hipGetLastError());
     }
+    bool all_gauss = true, consecutive = true;
     for (int r = 0; r < n_runs; ++r) {
-        if (runs[r].couplings == PA_GAUSS) st = launch_sweep_gauss(runs[r], *step, (hipStream_t)runs[r].stream);
+        all_gauss = all_gauss && runs[r].couplings == PA_GAUSS;
+        consecutive = consecutive && runs[r].state == runs[0].state + r && runs[r].stream == runs[0].stream;
+    }
+    if (all_gauss) return launch_sweep_gauss(runs, n_runs, consecutive, *step, (hipStream_t)runs[0].stream);
+    for (int r = 0; r < n_runs; ++r) {
+        if (runs[r].couplings == PA_GAUSS) st = launch_sweep_gauss(&runs[r], 1, false, *step, (hipStream_t)runs[r].stream);
         else st = launch_sweep(runs[r], *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }

@@ -82,9 +82,13 @@ __host__ __device__ inline WorkLayout work_layout(int64_t N, int64_t n_bins, int
     w.qhist = o;    o = align256(o + 8 * (size_t)(N + 1));
     w.misc = o;     o = align256(o + 8 * 64);
     w.batch = o;    o = align256(o + 8 * 1025);
-    w.total = o;
+    w.total = o;    // Gaussian couplings only: the sweep's threshold table starts here
     return w;
 }
+
+// bytes of the Gaussian sweep table after WorkLayout::total: u16 [colour][N / 2][64] (cube) or
+// [colour][N / 2][4] (chain), sized for the cube
+__host__ __device__ inline size_t gauss_table_bytes(int64_t N) { return 128 * (size_t)N; }
 
 template <typename T>
 __device__ inline T* work_ptr(const pa_state* st, size_t off)
@@ -152,10 +156,11 @@ __device__ inline double expd(double x)
     return ldexp(p, (int)k);
 }
 
-// Gaussian-coupling path (separate kernels; one run per launch)
+// Gaussian-coupling path (separate kernels; one run per launch but for the sweep)
 int gauss_couplings_upload(const pa_run& run, hipStream_t s);
 int launch_energy_gauss(const pa_run& run, int buf, int64_t n_replicas, hipStream_t s);
-int launch_sweep_gauss(const pa_run& run, const pa_step& step, hipStream_t s);
+// consecutive: the runs' states are consecutive and share runs[0].stream (one launch for all)
+int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const pa_step& step, hipStream_t s);
 int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s);
 int launch_measure_gauss(const pa_run& run, const pa_run* partner, hipStream_t s);
 int launch_moments_gauss(const pa_run& run, hipStream_t s);

@@ -156,6 +156,295 @@ __global__ void __launch_bounds__(64) k_sweep_gauss(const pa_state* __restrict__
     if (ns > 0) reinterpret_cast<double*>(st->energy[st->cur])[r] = energy_gauss(st, s);
 }
 
+// ------------------------------------------------------------------ tabled sweep
+// The same sweeps with lane = replica and a wave of 64 replicas.  Each lane keeps its spins as
+// 16-site segments in LDS (bit j of segment m is site 16m + j), so the neighbour bits of a whole
+// segment come from a few shifts of at most five segment words.
+//
+// dE of an attempt depends only on the site and on the pattern b of the bits s_j xor s_i of
+// its neighbours in field order: flipping every spin negates each term of h exactly, hence h,
+// and leaves dE unchanged.  Per call, k_gauss_table tabulates for every site and pattern
+// T16 = floor(p 2^16) with p = expd(-(beta dE)) computed as in k_sweep_gauss (s_i = 0, s_j = bit
+// of b), and 0xFFFF where the flip is always accepted (dE <= 0 or p >= 1).  An attempt compares
+// its 16-bit draw u with T16: u < T16 accepts, u > T16 rejects, and u == T16 (rare) recomputes p
+// for that lane and compares the 64-bit draw with floor(p 2^64), as k_sweep_gauss does.  The
+// outcome of every attempt is therefore the same as there.
+//
+// Table layout (after the work layout): u16 [colour c][h][pattern], h = i >> 1 for the site i of
+// colour c among i = 2h, 2h + 1 (rows have even length, so exactly one of the two has colour c).
+
+constexpr int kGaussWaves = 4;
+
+// h of site i for neighbour pattern b (bit a: neighbour a in field order has s_j != s_i)
+template <int NB>
+__device__ double gauss_field_pattern(const double* __restrict__ J, int i, int b, int L, int N)
+{
+    double h = 0.0;
+    if constexpr (NB == 2) {
+        const int im = i == 0 ? N - 1 : i - 1;
+        h = h + ((b & 1) ? -J[i] : J[i]);
+        h = h + ((b & 2) ? -J[im] : J[im]);
+    } else {
+        const int x = i % L, y = (i / L) % L, z = i / (L * L);
+        const int m[3] = {(x == 0 ? L - 1 : x - 1) + L * (y + L * z), x + L * ((y == 0 ? L - 1 : y - 1) + L * z),
+                          x + L * (y + L * (z == 0 ? L - 1 : z - 1))};
+        for (int a = 0; a < 3; ++a) h = h + (((b >> a) & 1) ? -J[3 * i + a] : J[3 * i + a]);
+        for (int a = 0; a < 3; ++a) h = h + (((b >> (3 + a)) & 1) ? -J[3 * m[a] + a] : J[3 * m[a] + a]);
+    }
+    return h;
+}
+
+// true if the flip is always accepted; otherwise *T64 = floor(p 2^64) with p < 1 (s_i = 0)
+__device__ inline bool gauss_threshold(double h, double beta, uint64_t* T64)
+{
+    const double dE = -2.0 * h;
+    if (dE <= 0.0) return true;
+    const double p = expd(-(beta * dE));
+    if (p >= 1.0) return true;
+    *T64 = (uint64_t)ldexp(p, 64);
+    return false;
+}
+
+__device__ __forceinline__ const uint16_t* gauss_table(const pa_state* st)
+{
+    return reinterpret_cast<const uint16_t*>(st->work + work_layout(st->N, st->n_bins, st->capacity).total);
+}
+
+// grid (entries / 256, runs): entry e = (c, h, b) of run blockIdx.y
+template <int NB>
+__global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ states, double beta)
+{
+    const pa_state* st = states + blockIdx.y;
+    if (st->status) return;
+    const int N = st->N, L = st->L;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (N << NB)) return;
+    const int half = (N / 2) << NB;
+    const int c = e >= half, rem = e - c * half;
+    const int hh = rem >> NB, b = rem & ((1 << NB) - 1);
+    const int i0 = 2 * hh;
+    const int col0 = NB == 2 ? 0 : ((i0 % L) + (i0 / L) % L + i0 / (L * L)) & 1;
+    const int i = i0 + (col0 != c);
+    uint64_t T64 = 0;
+    const bool always = gauss_threshold(gauss_field_pattern<NB>(reinterpret_cast<const double*>(st->J), i, b, L, N),
+                                        beta, &T64);
+    const_cast<uint16_t*>(gauss_table(st))[e] = always ? (uint16_t)0xFFFFu : (uint16_t)(T64 >> 48);
+}
+
+__device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t w)  // bytes b0..b3 in {0,1} -> b0 | b1<<1 | ...
+{
+    return (w * 0x10204080u) >> 28;
+}
+
+__device__ __forceinline__ uint32_t bits4_to_bytes(uint32_t n)  // inverse of bytes_to_bits4
+{
+    return (n * 0x00204081u) & 0x01010101u;
+}
+
+// the neighbour words of segment m in field order, each xor the segment itself
+template <int NB, int L>
+__device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__ seg, int m, int nseg, uint32_t D,
+                                                    uint32_t X[NB], int* par)
+{
+    if constexpr (NB == 2) {
+        const uint32_t Sn = seg[(m + 1 == nseg ? 0 : m + 1) * 64];
+        const uint32_t Sp = seg[(m == 0 ? nseg - 1 : m - 1) * 64];
+        X[0] = (((D >> 1) | (Sn << 15)) & 0xFFFFu) ^ D;
+        X[1] = (((D << 1) | (Sp >> 15)) & 0xFFFFu) ^ D;
+        *par = 0;
+    } else {
+        constexpr int SP = L * L / 16;  // segments per z plane
+        constexpr int NR = 16 / L;      // rows per segment
+        constexpr uint32_t Mhi = L == 4 ? 0x8888u : 0x8080u;  // x = L - 1
+        constexpr uint32_t Mlo = L == 4 ? 0x1111u : 0x0101u;  // x = 0
+        const int z = m / SP, q = m - z * SP;
+        const uint32_t Sn = seg[(z * SP + (q + 1 == SP ? 0 : q + 1)) * 64];
+        const uint32_t Sp = seg[(z * SP + (q == 0 ? SP - 1 : q - 1)) * 64];
+        const uint32_t Sz = seg[((z + 1 == L ? 0 : z + 1) * SP + q) * 64];
+        const uint32_t Szm = seg[((z == 0 ? L - 1 : z - 1) * SP + q) * 64];
+        X[0] = (((D >> 1) & ~Mhi) | ((D << (L - 1)) & Mhi)) ^ D;
+        X[1] = (((D >> L) | (Sn << (16 - L))) & 0xFFFFu) ^ D;
+        X[2] = Sz ^ D;
+        X[3] = (((D << 1) & ~Mlo & 0xFFFFu) | ((D >> (L - 1)) & Mlo)) ^ D;
+        X[4] = (((D << L) | (Sp >> (16 - L))) & 0xFFFFu) ^ D;
+        X[5] = Szm ^ D;
+        *par = (q * NR + z) & 1;
+    }
+}
+
+// one half-sweep over the SEL sites of segment m: sites j with colour parity SEL (chain: j & 1;
+// cube: (x + y) & 1 of the site inside the segment); T is the colour's table; returns the flips
+template <int NB, int L, int SEL>
+__device__ __forceinline__ uint32_t gauss_segment_attempts(const uint16_t* __restrict__ T, const uint32_t X[NB],
+                                                           const uint4v& v, int m, uint32_t* ties)
+{
+    uint32_t P[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) P[a] = X[a] << a;
+    uint32_t thi[16], F = 0, tie = 0;
+    const uint16_t* Tm = T + ((8 * m) << NB);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        int cj;
+        if constexpr (NB == 2) cj = j & 1;
+        else cj = ((j % L) + (j / L)) & 1;
+        if (cj != SEL) continue;
+        uint32_t acc = P[0] & (1u << j);
+#pragma unroll
+        for (int a = 1; a < NB; ++a) acc |= P[a] & (1u << (j + a));
+        thi[j] = Tm[((j >> 1) << NB) + (acc >> j)];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        int cj;
+        if constexpr (NB == 2) cj = j & 1;
+        else cj = ((j % L) + (j / L)) & 1;
+        if (cj != SEL) continue;
+        const uint32_t u = (word_of(v, j >> 2) >> (16 * ((j >> 1) & 1))) & 0xFFFFu;
+        F |= (uint32_t)(u < thi[j]) << j;
+        tie |= (uint32_t)(u == thi[j]) << j;
+    }
+    *ties = tie;
+    return F;
+}
+
+struct GaussWords { uint32_t w[6]; };
+
+// exact decision of the attempts in ties (u == T16): recompute p and compare 64-bit draws
+template <int NB>
+__device__ __attribute__((noinline)) uint32_t gauss_resolve_ties(const double* __restrict__ J, int L, int N, int m,
+                                                                  GaussWords X, uint4v v, uint32_t ties,
+                                                                  double beta, uint32_t rr, uint32_t ctr2,
+                                                                  uint32_t k0, uint32_t k1)
+{
+    uint32_t F = 0;
+    while (ties) {
+        const int j = __builtin_ctz(ties);
+        ties &= ties - 1;
+        int b = 0;
+        for (int a = 0; a < NB; ++a) b |= (int)((X.w[a] >> j) & 1u) << a;
+        const int i = 16 * m + j;
+        uint64_t T64 = 0;
+        bool accept = gauss_threshold(gauss_field_pattern<NB>(J, i, b, L, N), beta, &T64);
+        if (!accept) {
+            const uint32_t u = (word_of(v, j >> 2) >> (16 * ((j >> 1) & 1))) & 0xFFFFu;
+            const uint4v w = philox10((uint32_t)i, rr, ctr2, kTagTie, k0, k1);
+            const uint64_t U = ((uint64_t)u << 48) | (uint64_t)w.x | ((uint64_t)(w.y & 0xFFFFu) << 32);
+            accept = U < T64;
+        }
+        F |= (uint32_t)accept << j;
+    }
+    return F;
+}
+
+// 1-D grid of blocks of kGaussWaves independent waves; block -> (run, group of kGaussWaves tiles):
+// with 8 or more runs, the runs are split into 8 contiguous ranges and the blocks of range x are
+// those with id = x mod 8 (blocks go round-robin to the 8 XCDs, so a run's table stays in one
+// L2); LDS per wave: segments [N / 16][64]
+template <int NB, int L>
+__global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* __restrict__ states, int n_runs,
+                                                                      int groups, double beta, int64_t t0, int ns)
+{
+    int run, group;
+    if (n_runs >= 8) {
+        const int per_xcd = (n_runs + 7) / 8;
+        const int k = blockIdx.x >> 3;
+        run = (int)(blockIdx.x & 7) * per_xcd + k / groups;
+        group = k % groups;
+    } else {
+        run = blockIdx.x / groups;
+        group = blockIdx.x % groups;
+    }
+    if (run >= n_runs) return;
+    const pa_state* st = states + run;
+    if (st->status) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tile = (int64_t)group * kGaussWaves + wave;
+    const int64_t R = st->R;
+    if (tile * 64 >= R) return;
+    extern __shared__ uint16_t lds16[];
+    const int N = st->N, Ld = st->L;
+    const int nseg = N >> 4;
+    const double* __restrict__ J = reinterpret_cast<const double*>(st->J);
+    const uint16_t* __restrict__ Tab = gauss_table(st);
+    uint16_t* seg = lds16 + wave * nseg * 64 + lane;
+    const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
+    const int64_t r = tile * 64 + lane;
+    const bool valid = r < R;
+    uint8_t* row = (uint8_t*)st->spins[st->cur] + r * st->row_stride;
+#pragma unroll 1
+    for (int m = 0; m < nseg; ++m) {
+        uint32_t w = 0;
+        if (valid) {
+            const uint4 q = *reinterpret_cast<const uint4*>(row + 16 * m);
+            w = bytes_to_bits4(q.x) | (bytes_to_bits4(q.y) << 4) | (bytes_to_bits4(q.z) << 8) | (bytes_to_bits4(q.w) << 12);
+        }
+        seg[m * 64] = (uint16_t)w;
+    }
+    const uint32_t rr = (uint32_t)r;
+    for (int64_t t = t0; t < t0 + ns; ++t) {
+        for (int col = 0; col < 2; ++col) {
+            const uint32_t ctr2 = (uint32_t)(2 * t + col);
+            const uint16_t* T = Tab + (col ? ((N / 2) << NB) : 0);
+#pragma unroll 1
+            for (int m = 0; m < nseg; ++m) {
+                const uint32_t D = seg[m * 64];
+                uint32_t X[NB];
+                int par;
+                gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
+                const uint4v v = philox10((uint32_t)m, rr, ctr2, kTagMet, k0, k1);
+                uint32_t ties, F;
+                if ((par ^ col) == 0) F = gauss_segment_attempts<NB, L, 0>(T, X, v, m, &ties);
+                else F = gauss_segment_attempts<NB, L, 1>(T, X, v, m, &ties);
+                if (ties) {
+                    GaussWords xw = {};
+#pragma unroll
+                    for (int a = 0; a < NB; ++a) xw.w[a] = X[a];
+                    F |= gauss_resolve_ties<NB>(J, Ld, N, m, xw, v, ties, beta, rr, ctr2, k0, k1);
+                }
+                seg[m * 64] = (uint16_t)(D ^ F);
+            }
+        }
+    }
+    // write back; E in bond order (site i, then axis +x, +y, +z; chain: bond i -- i+1)
+    double E = 0.0;
+#pragma unroll 1
+    for (int m = 0; m < nseg; ++m) {
+        const uint32_t D = seg[m * 64];
+        uint32_t X[NB];
+        int par;
+        gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
+        const double* Jm = J + (NB == 2 ? 16 * m : 48 * m);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if constexpr (NB == 2) {
+                E = E + (((X[0] >> j) & 1u) ? -Jm[j] : Jm[j]);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) E = E + (((X[a] >> j) & 1u) ? -Jm[3 * j + a] : Jm[3 * j + a]);
+            }
+        }
+        if (valid) {
+            uint4 q;
+            q.x = bits4_to_bytes(D & 15u);
+            q.y = bits4_to_bytes((D >> 4) & 15u);
+            q.z = bits4_to_bytes((D >> 8) & 15u);
+            q.w = bits4_to_bytes((D >> 12) & 15u);
+            *reinterpret_cast<uint4*>(row + 16 * m) = q;
+        }
+    }
+    if (valid) reinterpret_cast<double*>(st->energy[st->cur])[r] = E;
+}
+
+// the tabled kernels cover cubes of side 4 and 8 and chains of N = 16 k <= 1024 sites
+static bool gauss_tab_shape(int dim, int L, int* NB)
+{
+    if (dim == 3 && (L == 4 || L == 8)) *NB = 6;
+    else if (dim == 1 && L % 16 == 0 && L <= 1024) *NB = 2;
+    else return false;
+    return true;
+}
+
 // energy mean, variance, skewness of the population (one block; any summation order: these are
 // compared to 1e-12, not bit for bit)
 __global__ void __launch_bounds__(256) k_moments_gauss(pa_state* st)
@@ -202,11 +491,54 @@ int launch_energy_gauss(const pa_run& run, int buf, int64_t n, hipStream_t s)
     return hip_status(hipGetLastError());
 }
 
-int launch_sweep_gauss(const pa_run& run, const pa_step& step, hipStream_t s)
+int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const pa_step& step, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sweep_gauss, dim3((unsigned)((run.capacity + 63) / 64)), dim3(64), 0, s,
-                       (const pa_state*)run.state, step.beta_to, step.t0, step.n_sweeps);
-    return hip_status(hipGetLastError());
+    int NB = 0;
+    bool tab = gauss_tab_shape(runs[0].dim, runs[0].L, &NB);
+    for (int r = 0; r < n_runs; ++r)
+        tab = tab && runs[r].dim == runs[0].dim && runs[r].L == runs[0].L && ((uintptr_t)runs[r].spins[0] & 15) == 0 &&
+              ((uintptr_t)runs[r].spins[1] & 15) == 0;
+    if (!tab) {
+        for (int r = 0; r < n_runs; ++r) {
+            hipLaunchKernelGGL(k_sweep_gauss, dim3((unsigned)((runs[r].capacity + 63) / 64)), dim3(64), 0,
+                               (hipStream_t)runs[r].stream, (const pa_state*)runs[r].state, step.beta_to, step.t0,
+                               step.n_sweeps);
+            const int st = hip_status(hipGetLastError());
+            if (st != PA_OK) return st;
+        }
+        return PA_OK;
+    }
+    const int dim = runs[0].dim, L = runs[0].L;
+    const int N = dim == 1 ? L : L * L * L;
+    const size_t lds = (size_t)kGaussWaves * (N / 16) * 64 * 2;
+    auto go = [&](pa_state* base, int n, int64_t capacity, hipStream_t str) {
+        const dim3 tgrid((unsigned)(((N << NB) + 255) / 256), (unsigned)n);
+        if (NB == 2) hipLaunchKernelGGL(k_gauss_table<2>, tgrid, dim3(256), 0, str, base, step.beta_to);
+        else hipLaunchKernelGGL(k_gauss_table<6>, tgrid, dim3(256), 0, str, base, step.beta_to);
+        int st = hip_status(hipGetLastError());
+        if (st != PA_OK) return st;
+        const int groups = (int)((capacity / 64 + kGaussWaves - 1) / kGaussWaves);
+        const int64_t blocks = n >= 8 ? (int64_t)8 * ((n + 7) / 8) * groups : (int64_t)n * groups;
+        if (blocks > INT32_MAX) return PA_ERR_ARG;
+        const dim3 grid((unsigned)blocks), block(kGaussWaves * 64);
+        if (dim == 1)
+            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+        else if (L == 4)
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 4>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+        else
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 8>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+        return hip_status(hipGetLastError());
+    };
+    if (consecutive) {
+        int64_t cap = 0;
+        for (int r = 0; r < n_runs; ++r) cap = runs[r].capacity > cap ? runs[r].capacity : cap;
+        return go(runs[0].state, n_runs, cap, (hipStream_t)runs[0].stream);
+    }
+    for (int r = 0; r < n_runs; ++r) {
+        const int st = go(runs[r].state, 1, runs[r].capacity, (hipStream_t)runs[r].stream);
+        if (st != PA_OK) return st;
+    }
+    return PA_OK;
 }
 
 int launch_moments_gauss(const pa_run& run, hipStream_t s)

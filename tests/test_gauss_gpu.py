@@ -41,7 +41,13 @@ def test_couplings_and_initial_population(dim, L):
     assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
 
 
-@pytest.mark.parametrize("dim,L,R,beta", [(1, 16, 130, 0.7), (3, 4, 300, 0.7), (3, 4, 77, 3.0), (3, 6, 65, 0.0)])
+# cubes of side 4 and 8 and chains of 16 k sites take the tabled kernel (ragged last tiles, several
+# blocks); side 6 and the chain of 40 take the per-replica kernel
+SWEEP_CASES = [(1, 16, 130, 0.7), (3, 4, 300, 0.7), (3, 4, 77, 3.0), (3, 6, 65, 0.0), (3, 6, 130, 1.3),
+               (3, 8, 1000, 0.7), (3, 8, 2100, 2.5), (3, 8, 64, 0.0), (1, 256, 300, 5.0), (1, 40, 90, 1.0)]
+
+
+@pytest.mark.parametrize("dim,L,R,beta", SWEEP_CASES)
 def test_sweep_matches_oracle(dim, L, R, beta):
     note(f"gauss sweep dim={dim} L={L} R={R} beta={beta}")
     run = gauss_run(dim, L, R, 5, 9)
@@ -81,7 +87,7 @@ def test_copy_numbers_match_oracle():
     assert np.array_equal(s, s_o[keep]) and np.array_equal(E, E_o[keep])
 
 
-@pytest.mark.parametrize("dim,L,R0,nT", [(3, 4, 200, 7), (1, 32, 300, 9)])
+@pytest.mark.parametrize("dim,L,R0,nT", [(3, 4, 200, 7), (1, 32, 300, 9), (3, 8, 500, 9), (1, 256, 400, 11)])
 def test_whole_run_matches_oracle(dim, L, R0, nT):
     note(f"gauss run dim={dim} L={L} R0={R0}")
     betas = [2.5 * k / (nT - 1) for k in range(nT)]
@@ -114,6 +120,31 @@ def test_whole_run_matches_oracle(dim, L, R0, nT):
     fe = torch.zeros(1, dtype=torch.float64, device=DEV)
     run.free_energy(fe)
     assert abs(fe.item() - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
+
+
+def test_batch_matches_oracle():
+    # one launch of the tabled sweep over four consecutive runs, two realizations
+    note("gauss batch of 4, L=8")
+    specs = [dict(dim=3, L=8, R0=R0, seed=40 + i, disorder_seed=1 + (i & 1), couplings="gauss")
+             for i, R0 in enumerate((300, 700, 1000, 64))]
+    nT, ns = 6, 2
+    betas = [3.0 * k / (nT - 1) for k in range(nT)]
+    batch = pa.Batch(specs, nT, layout="u8", device=DEV)
+    batch.init()
+    sched = pa.Schedule(betas, ns, batch.runs[0].n_bins, device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k)
+    code, flags = batch.status()
+    assert code == pa.PA_OK and not flags.any()
+    for sp, run in zip(specs, batch.runs):
+        J = o.couplings_gauss(3, 8, sp["disorder_seed"])
+        st_o, rec_o, s_o, E_o = o.run_gauss(3, 8, J, sp["seed"], sp["R0"], betas, ns, capacity=run.capacity)
+        assert st_o == 0
+        s, E = run.population()
+        assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+        rec = run.records()
+        assert np.array_equal(rec[:, 4], rec_o[:, 1])
+        assert abs(rec[-1, 2] - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
 
 
 def test_overlap_of_gaussian_pair():
