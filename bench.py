@@ -51,11 +51,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "stepped"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "stepped", "gauss"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
                         "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
                         "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs); "
-                        "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work")
+                        "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work; "
+                        "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
@@ -250,6 +251,67 @@ def bench_stepped(args):
     print(json.dumps(out), flush=True)
 
 
+# algorithmic VALU work per tabled Gaussian attempt, lane-ops: 1/8 of a Philox call (5), the
+# 6-bit neighbour pattern (one op per neighbour) and the table compare and flip (3)
+OPS_PER_ATTEMPT_GAUSS = 40 / 8 + 6 + 3
+
+
+def cpu_baseline_gauss(L, n_sweeps, target_s):
+    """The oracle's Gaussian sweep on the first replicas of the L = 8 ensemble's first run, beta = 1."""
+    from oracle import oracle as o
+
+    J = o.couplings_gauss(3, L, 1)
+    threads = o.num_threads()
+    n = max(threads, 16)
+    s, E = o.init_replicas_gauss(3, L, J, 1, 0, n)
+    t = time.perf_counter()
+    o.sweep_replicas_gauss(3, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
+    per_rep = (time.perf_counter() - t) / n
+    m = int(max(threads, target_s / max(per_rep, 1e-9)))
+    s, E = o.init_replicas_gauss(3, L, J, 1, 0, m)
+    t = time.perf_counter()
+    o.sweep_replicas_gauss(3, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
+    dt = time.perf_counter() - t
+    attempts = m * L ** 3 * n_sweeps
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Gaussian sweep of {m} replicas of the L={L} cube, {n_sweeps} sweeps at beta=1 "
+                      f"({attempts:.3e} attempts in {dt:.1f} s)"}
+
+
+def bench_gauss(args):
+    """Sec. IV's 3D Gaussian ensemble: L = 8, R = 2000, 100 temperatures evenly spaced in T from 2
+    to 0.2 (the random start equilibrated at T = 2), 100 sweeps per temperature, 126 runs of one realization (the
+    paper's 125-run ensemble of its worst realization, rounded up to whole pairs for the overlap),
+    all runs one batch.  value = attempts/s of
+    the whole hot path (resample, sweep, measure with pair overlaps) over the 99 steps and the 100
+    sweep blocks; the free energies are relative to T = 2."""
+    from paper_1006_0252_amd import gauss3d
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    gauss3d.run(M=4, R=200, n_temps=3, n_sweeps=2)            # warm-up: module load, first launches
+    r = gauss3d.run(log=log)
+    n_steps = r["n_steps"]
+    sweep_s = float(r["sweep_ms"].sum()) / 1e3
+    rate = r["attempts"] / sweep_s
+    achieved = rate * OPS_PER_ATTEMPT_GAUSS
+    out = {
+        "metric": METRIC, "value": r["attempts"] / r["wall_seconds"], "unit": "attempts/s", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0, "ms_per_step": r["wall_seconds"] / n_steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "gauss3d_L8_R2000_126runs", "L": 8, "R": 2000, "n_temps": 100, "T": [2.0, 0.2],
+                   "n_sweeps": 100, "runs": 126, "disorder_seed": 1, "layout": "u8"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "T lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "k_gauss_table + k_sweep_gauss_tab (HIP events around pa_sweep)",
+                     "ops_per_attempt": OPS_PER_ATTEMPT_GAUSS, "sweep_attempts_per_s": rate},
+        "physics": {"free_energy_reference": "T=2", "minus_betaF_bar": r["minus_betaF_bar"], "var_betaF": r["var_betaF"],
+                    "mean_minus_betaF": r["mean_minus_betaF"], "E_bar": r["E_bar"], "gamma_bar": r["gamma_bar"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_gauss(8, 100, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -295,6 +357,9 @@ def main():
         return
     if args.workload == "stepped":
         bench_stepped(args)
+        return
+    if args.workload == "gauss":
+        bench_gauss(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1

@@ -35,18 +35,25 @@ static int check_run(const pa_run& r)
     return PA_OK;
 }
 
-// one launch per kernel for all runs: consecutive device states, one stream, one layout
-static bool batchable(const pa_run* runs, int n)
+// one launch per kernel for all runs: consecutive device states, one stream, one layout, one
+// kind of couplings
+static bool consecutive_runs(const pa_run* runs, int n)
 {
     if (n < 2) return false;
-    for (int r = 0; r < n; ++r)
-        if (runs[r].couplings == PA_GAUSS) return false;  // Gaussian runs: one launch per run
     for (int r = 1; r < n; ++r) {
         if (runs[r].state != runs[0].state + r) return false;
-        if (runs[r].stream != runs[0].stream || runs[r].layout != runs[0].layout || runs[r].dim != runs[0].dim)
+        if (runs[r].stream != runs[0].stream || runs[r].layout != runs[0].layout || runs[r].dim != runs[0].dim ||
+            runs[r].couplings != runs[0].couplings)
             return false;
     }
     return true;
+}
+
+static bool batchable(const pa_run* runs, int n) { return consecutive_runs(runs, n) && runs[0].couplings == PA_PM1; }
+
+static bool batchable_gauss(const pa_run* runs, int n)
+{
+    return consecutive_runs(runs, n) && runs[0].couplings == PA_GAUSS;
 }
 
 static int check_step(const pa_step* s, bool need_weights)
@@ -177,8 +184,9 @@ int pa_resample(pa_run* runs, int n_runs, const pa_step* step)
         if (step->n_weights < sz.n_bins || step->k >= runs[r].n_records) return PA_ERR_ARG;
     }
     if (batchable(runs, n_runs)) return launch_resample(runs, n_runs, *step, (hipStream_t)runs[0].stream);
+    if (batchable_gauss(runs, n_runs)) return launch_resample_gauss(runs, n_runs, *step, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {
-        if (runs[r].couplings == PA_GAUSS) st = launch_resample_gauss(runs[r], *step, (hipStream_t)runs[r].stream);
+        if (runs[r].couplings == PA_GAUSS) st = launch_resample_gauss(&runs[r], 1, *step, (hipStream_t)runs[r].stream);
         else st = launch_resample(&runs[r], 1, *step, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
@@ -197,19 +205,21 @@ int pa_measure(pa_run* runs, int n_runs, const int32_t* partner)
             if (p.dim != runs[r].dim || p.L != runs[r].L || p.layout != runs[r].layout) return PA_ERR_ARG;
         }
     }
-    if (batchable(runs, n_runs)) {
+    if (batchable(runs, n_runs) || batchable_gauss(runs, n_runs)) {
         // partners either absent or the pairs (0,1), (2,3), ...: one launch per kernel
         bool none = partner == nullptr, pairs = partner != nullptr && n_runs % 2 == 0;
         for (int r = 0; partner && r < n_runs; ++r) {
             if (partner[r] >= 0) none = false;
             if (partner[r] != (r ^ 1)) pairs = false;
         }
-        if (none) return launch_measure(runs, n_runs, nullptr, 0, (hipStream_t)runs[0].stream);
-        if (pairs) return launch_measure(runs, n_runs, nullptr, 1, (hipStream_t)runs[0].stream);
+        const bool g = runs[0].couplings == PA_GAUSS;
+        hipStream_t s0 = (hipStream_t)runs[0].stream;
+        if (none) return g ? launch_measure_gauss(runs, n_runs, nullptr, 0, s0) : launch_measure(runs, n_runs, nullptr, 0, s0);
+        if (pairs) return g ? launch_measure_gauss(runs, n_runs, nullptr, 1, s0) : launch_measure(runs, n_runs, nullptr, 1, s0);
     }
     for (int r = 0; r < n_runs; ++r) {
         const pa_run* p = (partner && partner[r] >= 0) ? &runs[partner[r]] : nullptr;
-        int st = runs[r].couplings == PA_GAUSS ? launch_measure_gauss(runs[r], p, (hipStream_t)runs[r].stream)
+        int st = runs[r].couplings == PA_GAUSS ? launch_measure_gauss(&runs[r], 1, p, 0, (hipStream_t)runs[r].stream)
                                                : launch_measure(&runs[r], 1, p, 0, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;
     }
@@ -223,7 +233,7 @@ int pa_free_energy(const pa_run* runs, int n_runs, double* minus_betaF_dev)
         int st = check_run(runs[r]);
         if (st != PA_OK) return st;
     }
-    if (batchable(runs, n_runs)) return launch_free_energy(runs, n_runs, minus_betaF_dev, (hipStream_t)runs[0].stream);
+    if (consecutive_runs(runs, n_runs)) return launch_free_energy(runs, n_runs, minus_betaF_dev, (hipStream_t)runs[0].stream);
     for (int r = 0; r < n_runs; ++r) {
         int st = launch_free_energy(&runs[r], 1, minus_betaF_dev + r, (hipStream_t)runs[r].stream);
         if (st != PA_OK) return st;

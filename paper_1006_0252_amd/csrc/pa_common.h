@@ -156,13 +156,13 @@ __device__ inline double expd(double x)
     return ldexp(p, (int)k);
 }
 
-// Gaussian-coupling path (separate kernels; one run per launch but for the sweep)
+// Gaussian-coupling path (separate kernels; n > 1 runs: consecutive states on one stream)
 int gauss_couplings_upload(const pa_run& run, hipStream_t s);
 int launch_energy_gauss(const pa_run& run, int buf, int64_t n_replicas, hipStream_t s);
 // consecutive: the runs' states are consecutive and share runs[0].stream (one launch for all)
 int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const pa_step& step, hipStream_t s);
-int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s);
-int launch_measure_gauss(const pa_run& run, const pa_run* partner, hipStream_t s);
-int launch_moments_gauss(const pa_run& run, hipStream_t s);
+int launch_resample_gauss(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
+int launch_measure_gauss(const pa_run* runs, int n, const pa_run* partner, int pair_xor, hipStream_t s);
+int launch_moments_gauss(const pa_run* runs, int n, hipStream_t s);
 
 }  // namespace pa

@@ -447,8 +447,9 @@ static bool gauss_tab_shape(int dim, int L, int* NB)
 
 // energy mean, variance, skewness of the population (one block; any summation order: these are
 // compared to 1e-12, not bit for bit)
-__global__ void __launch_bounds__(256) k_moments_gauss(pa_state* st)
+__global__ void __launch_bounds__(256) k_moments_gauss(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     __shared__ double red[256];
     const int64_t R = st->R;
@@ -541,9 +542,9 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
     return PA_OK;
 }
 
-int launch_moments_gauss(const pa_run& run, hipStream_t s)
+int launch_moments_gauss(const pa_run* runs, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_moments_gauss, dim3(1), dim3(256), 0, s, run.state);
+    hipLaunchKernelGGL(k_moments_gauss, dim3(1, (unsigned)n), dim3(256), 0, s, runs[0].state);
     return hip_status(hipGetLastError());
 }
 

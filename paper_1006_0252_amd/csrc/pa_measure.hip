@@ -174,17 +174,22 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
     return hip_status(hipGetLastError());
 }
 
-// Gaussian couplings: energy moments from the FP64 energies, overlap as for one byte per spin
-int launch_measure_gauss(const pa_run& run, const pa_run* partner, hipStream_t s)
+// Gaussian couplings: energy moments from the FP64 energies, overlap as for one byte per spin;
+// runs as for launch_measure (consecutive states when n > 1)
+int launch_measure_gauss(const pa_run* runs, int n, const pa_run* partner, int pair_xor, hipStream_t s)
 {
-    int rc = launch_moments_gauss(run, s);
-    if (rc != PA_OK || !partner) return rc;
-    const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
-    pa_state* base = run.state;
-    hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), 1), dim3(256), 0, s, base);
-    hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((run.capacity + 3) / 4), 1), dim3(256), 0, s, base,
-                       (const pa_state*)partner->state, 0);
-    hipLaunchKernelGGL(k_overlap_stats, dim3(1, 1), dim3(1), 0, s, base, (const pa_state*)partner->state, 0);
+    int rc = launch_moments_gauss(runs, n, s);
+    if (rc != PA_OK || !(partner || pair_xor)) return rc;
+    int64_t N = 0, P = 0;
+    for (int r = 0; r < n; ++r) {
+        N = std::max<int64_t>(N, runs[r].dim == 1 ? runs[r].L : (int64_t)runs[r].L * runs[r].L * runs[r].L);
+        P = std::max<int64_t>(P, runs[r].capacity);
+    }
+    pa_state* base = runs[0].state;
+    const pa_state* bg = partner ? partner->state : nullptr;
+    hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), n), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
+    hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(1), 0, s, base, bg, pair_xor);
     return hip_status(hipGetLastError());
 }
 

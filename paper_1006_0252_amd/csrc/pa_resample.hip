@@ -517,8 +517,9 @@ int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t 
 constexpr int kMiscGaussS = 3;      // misc slot: S (FP64 bits)
 constexpr int kGaussBlock = 256;
 
-__global__ void __launch_bounds__(256) k_gauss_min(pa_state* st)
+__global__ void __launch_bounds__(256) k_gauss_min(pa_state* base)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     __shared__ double red[256];
     const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
@@ -537,8 +538,9 @@ __global__ void __launch_bounds__(256) k_gauss_min(pa_state* st)
 }
 
 // thread per block of 256 replicas: its in-order weight sum, kept in the source-index area
-__global__ void __launch_bounds__(256) k_gauss_blocksum(pa_state* st, double dbeta)
+__global__ void __launch_bounds__(256) k_gauss_blocksum(pa_state* base, double dbeta)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t R = st->R;
@@ -553,8 +555,9 @@ __global__ void __launch_bounds__(256) k_gauss_blocksum(pa_state* st, double dbe
     work_ptr<double>(st, wl.src)[b] = part;
 }
 
-__global__ void k_gauss_normalise(pa_state* st, ResampleParams p)
+__global__ void k_gauss_normalise(pa_state* base, ResampleParams p)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     int64_t* misc = work_ptr<int64_t>(st, wl.misc);
@@ -580,8 +583,9 @@ __global__ void k_gauss_normalise(pa_state* st, ResampleParams p)
     *reinterpret_cast<double*>(&misc[kMiscGaussS]) = S;
 }
 
-__global__ void __launch_bounds__(256) k_gauss_copies(pa_state* st, ResampleParams p)
+__global__ void __launch_bounds__(256) k_gauss_copies(pa_state* base, ResampleParams p)
 {
+    pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= st->R) return;
@@ -619,7 +623,8 @@ __global__ void __launch_bounds__(256) k_gauss_copies(pa_state* st, ResamplePara
     st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
 }
 
-int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s)
+// runs: n runs with consecutive states on one stream (grid.y = run), or a single run
+int launch_resample_gauss(const pa_run* runs, int n, const pa_step& step, hipStream_t s)
 {
     ResampleParams p;
     p.beta_from = step.beta_from;
@@ -627,24 +632,29 @@ int launch_resample_gauss(const pa_run& run, const pa_step& step, hipStream_t s)
     p.R_target = step.R_target;
     p.w = nullptr;
     p.k = step.k;
-    pa_state* st = run.state;
-    const int64_t cap = run.capacity;
+    pa_state* base = runs[0].state;
+    int64_t cap = 0, stride = 0;
+    for (int r = 0; r < n; ++r) {
+        const int64_t N = runs[r].dim == 1 ? runs[r].L : (int64_t)runs[r].L * runs[r].L * runs[r].L;
+        cap = std::max<int64_t>(cap, runs[r].capacity);
+        stride = std::max<int64_t>(stride, (N + 15) / 16 * 16);
+    }
     const unsigned cap_blocks = (unsigned)((cap + 255) / 256);
     const unsigned n_scan = (unsigned)((cap + kScanTile - 1) / kScanTile);
     const int64_t n_part = (cap + kGaussBlock - 1) / kGaussBlock;
-    hipLaunchKernelGGL(k_gauss_min, dim3(1), dim3(256), 0, s, st);
-    hipLaunchKernelGGL(k_gauss_blocksum, dim3((unsigned)((n_part + 255) / 256)), dim3(256), 0, s, st,
+    const unsigned ny = (unsigned)n;
+    hipLaunchKernelGGL(k_gauss_min, dim3(1, ny), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_gauss_blocksum, dim3((unsigned)((n_part + 255) / 256), ny), dim3(256), 0, s, base,
                        step.beta_to - step.beta_from);
-    hipLaunchKernelGGL(k_gauss_normalise, dim3(1), dim3(1), 0, s, st, p);
-    hipLaunchKernelGGL(k_gauss_copies, dim3(cap_blocks), dim3(256), 0, s, st, p);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, 1), dim3(256), 0, s, st);
-    hipLaunchKernelGGL(k_scan_top, dim3(1, 1), dim3(256), 0, s, st);
-    hipLaunchKernelGGL(k_scan_down, dim3(n_scan, 1), dim3(256), 0, s, st);
-    hipLaunchKernelGGL(k_src, dim3(cap_blocks, 1), dim3(256), 0, s, st);
-    const int64_t N = run.dim == 1 ? run.L : (int64_t)run.L * run.L * run.L;
-    const int64_t threads = cap * (((N + 15) / 16 * 16) / 16);  // one per 16 bytes of a row
-    hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, s, st);
-    hipLaunchKernelGGL(k_finish, dim3(1, 1), dim3(1), 0, s, st, p);
+    hipLaunchKernelGGL(k_gauss_normalise, dim3(1, ny), dim3(1), 0, s, base, p);
+    hipLaunchKernelGGL(k_gauss_copies, dim3(cap_blocks, ny), dim3(256), 0, s, base, p);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, ny), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, ny), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_scan_down, dim3(n_scan, ny), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_src, dim3(cap_blocks, ny), dim3(256), 0, s, base);
+    const int64_t threads = cap * (stride / 16);  // one per 16 bytes of a row
+    hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256), ny), dim3(256), 0, s, base);
+    hipLaunchKernelGGL(k_finish, dim3(1, ny), dim3(1), 0, s, base, p);
     return hip_status(hipGetLastError());
 }
 

@@ -222,6 +222,15 @@ class Schedule:
         s.n_weights = self.n_bins
         return s
 
+    def start_sweeps(self):
+        """pa_step (for pa_sweep only) of n_sweeps at betas[0], for a schedule that starts at a
+        finite temperature: the random initial population is equilibrated there first.  Its sweep
+        indices follow those of the schedule's steps, so its draws are distinct from theirs."""
+        s = self.step(1)
+        s.beta_from = s.beta_to = float(self.betas[0])
+        s.t0 = (len(self.betas) - 1) * self.n_sweeps
+        return s
+
 
 class Run:
     """One population-annealing run: caller-owned torch buffers described by a pa_run."""

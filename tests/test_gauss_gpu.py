@@ -122,20 +122,27 @@ def test_whole_run_matches_oracle(dim, L, R0, nT):
     assert abs(fe.item() - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
 
 
-def test_batch_matches_oracle():
-    # one launch of the tabled sweep over four consecutive runs, two realizations
-    note("gauss batch of 4, L=8")
-    specs = [dict(dim=3, L=8, R0=R0, seed=40 + i, disorder_seed=1 + (i & 1), couplings="gauss")
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(graph):
+    # one launch per kernel over four consecutive runs (two realizations, pairs (0,1) and (2,3)),
+    # stepped eagerly or replayed once from a captured graph
+    note(f"gauss batch of 4, L=8, graph={graph}")
+    specs = [dict(dim=3, L=8, R0=R0, seed=40 + i, disorder_seed=1 + (i >> 1), couplings="gauss")
              for i, R0 in enumerate((300, 700, 1000, 64))]
     nT, ns = 6, 2
     betas = [3.0 * k / (nT - 1) for k in range(nT)]
     batch = pa.Batch(specs, nT, layout="u8", device=DEV)
     batch.init()
     sched = pa.Schedule(betas, ns, batch.runs[0].n_bins, device=DEV)
-    for k in range(1, nT):
-        batch.step(sched, k)
+    if graph:
+        g = batch.capture(sched, range(1, nT), pairs=True)
+        g.launch()
+    else:
+        for k in range(1, nT):
+            batch.step(sched, k, pairs=True)
     code, flags = batch.status()
     assert code == pa.PA_OK and not flags.any()
+    pops = []
     for sp, run in zip(specs, batch.runs):
         J = o.couplings_gauss(3, 8, sp["disorder_seed"])
         st_o, rec_o, s_o, E_o = o.run_gauss(3, 8, J, sp["seed"], sp["R0"], betas, ns, capacity=run.capacity)
@@ -144,7 +151,17 @@ def test_batch_matches_oracle():
         assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
         rec = run.records()
         assert np.array_equal(rec[:, 4], rec_o[:, 1])
-        assert abs(rec[-1, 2] - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
+        for k in range(1, nT):
+            assert abs(rec[k, 2] - rec_o[k, 3]) <= 1e-12 * max(1.0, abs(rec_o[k, 3]))
+            assert abs(rec[k, 6] - rec_o[k, 4]) <= 1e-12 * max(1.0, abs(rec_o[k, 4]))
+        pops.append(s_o)
+    for r, run in enumerate(batch.runs):
+        h, P = o.overlap_hist(512, pops[r], pops[r ^ 1])
+        q2, q4, gm = o.overlap_stats(512, h)
+        rec = run.records()[nT - 1]
+        assert rec[12] == P
+        for got, want in zip(rec[9:12], (q2, q4, gm)):
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
 
 
 def test_overlap_of_gaussian_pair():
@@ -178,3 +195,34 @@ def test_gaussian_rejected_where_unsupported():
     t = np.array([0.2])
     out = torch.zeros(1, dtype=torch.float64, device=DEV)
     assert pa.lib().pa_rho_steps(ctypes.byref(run.desc), 1, pa._np(t), 1, 1.0, 1, out.data_ptr()) == pa.PA_ERR_ARG
+
+
+def test_start_sweeps_then_steps_match_oracle():
+    # a schedule that starts at T = 2: the random start is swept there first, with sweep indices
+    # after those of the steps, then annealed
+    note("gauss start at T=2")
+    betas = 1.0 / np.linspace(2.0, 0.5, 5)
+    ns, R0 = 3, 400
+    run = gauss_run(3, 8, R0, 77, 5, n_records=len(betas), capacity=768)
+    sched = pa.Schedule(betas, ns, run.n_bins, device=DEV)
+    run.sweep(sched.start_sweeps())
+    J = o.couplings_gauss(3, 8, 5)
+    s_o, E_o = o.init_replicas_gauss(3, 8, J, 77, 0, R0)
+    o.sweep_replicas_gauss(3, 8, J, 77, betas[0], 0, s_o, E_o, (len(betas) - 1) * ns, ns)
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+    for k in range(1, len(betas)):
+        st = sched.step(k)
+        run.resample(st)
+        run.sweep(st)
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    for k in range(1, len(betas)):
+        st_o, c, S, lnQ, _ = o.copy_numbers_gauss(77, k, betas[k - 1], betas[k], float(R0), E_o)
+        assert st_o == 0
+        keep = np.repeat(np.arange(len(E_o)), c)
+        s_o, E_o = np.ascontiguousarray(s_o[keep]), np.ascontiguousarray(E_o[keep])
+        o.sweep_replicas_gauss(3, 8, J, 77, betas[k], 0, s_o, E_o, (k - 1) * ns, ns)
+        assert abs(run.records()[k][1] - lnQ) <= 1e-12 * max(1.0, abs(lnQ))
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
