@@ -272,37 +272,72 @@ __device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__
     }
 }
 
-// one half-sweep over the SEL sites of segment m: sites j with colour parity SEL (chain: j & 1;
-// cube: (x + y) & 1 of the site inside the segment); T is the colour's table; returns the flips
+// the k-th site (k = 0..7, ascending) of colour parity SEL inside a segment (chain: j & 1; cube:
+// (x + y) & 1 of the site inside the segment)
 template <int NB, int L, int SEL>
-__device__ __forceinline__ uint32_t gauss_segment_attempts(const uint16_t* __restrict__ T, const uint32_t X[NB],
-                                                           const uint4v& v, int m, uint32_t* ties)
+__host__ __device__ constexpr int seg_site(int k)
 {
+    int c = 0;
+    for (int j = 0; j < 16; ++j) {
+        const int cj = NB == 2 ? (j & 1) : (((j % L) + (j / L)) & 1);
+        if (cj == SEL) {
+            if (c == k) return j;
+            ++c;
+        }
+    }
+    return -1;
+}
+
+// sites k and k + 4 are gathered together: their NB-bit fields must not overlap
+template <int NB, int L, int SEL>
+__host__ __device__ constexpr bool seg_pairs_ok()
+{
+    for (int k = 0; k < 4; ++k)
+        if (seg_site<NB, L, SEL>(k + 4) - seg_site<NB, L, SEL>(k) < NB) return false;
+    return true;
+}
+
+typedef const __attribute__((address_space(1))) uint16_t* gtab_ptr;
+
+// first half of the attempts of segment m: the table entries of its 8 sites of colour parity SEL,
+// in site order; the loads stay in flight until the entries are used
+template <int NB, int L, int SEL>
+__device__ __forceinline__ void gauss_segment_lookup(gtab_ptr Tm, const uint32_t X[NB], uint32_t thi[8])
+{
+    static_assert(seg_pairs_ok<NB, L, SEL>(), "paired sites overlap");
     uint32_t P[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) P[a] = X[a] << a;
-    uint32_t thi[16], F = 0, tie = 0;
-    const uint16_t* Tm = T + ((8 * m) << NB);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        int cj;
-        if constexpr (NB == 2) cj = j & 1;
-        else cj = ((j % L) + (j / L)) & 1;
-        if (cj != SEL) continue;
-        uint32_t acc = P[0] & (1u << j);
+    for (int k = 0; k < 4; ++k) {
+        const int j = seg_site<NB, L, SEL>(k), jp = seg_site<NB, L, SEL>(k + 4);
+        uint32_t acc = 0;
 #pragma unroll
-        for (int a = 1; a < NB; ++a) acc |= P[a] & (1u << (j + a));
-        thi[j] = Tm[((j >> 1) << NB) + (acc >> j)];
+        for (int a = 0; a < NB; ++a) acc |= P[a] & ((1u << (j + a)) | (1u << (jp + a)));
+        constexpr uint32_t mask = (1u << NB) - 1;
+        thi[k] = Tm[((j >> 1) << NB) + ((acc >> j) & mask)];
+        thi[k + 4] = Tm[((jp >> 1) << NB) + ((acc >> jp) & mask)];
     }
+}
+
+// second half: u < T16 accepts, and any u == T16 is reported in *ties (site bits); returns the flips
+template <int NB, int L, int SEL>
+__device__ __forceinline__ uint32_t gauss_segment_decide(const uint32_t thi[8], const uint4v& v, uint32_t* ties)
+{
+    uint32_t F = 0, dmin = 0xFFFFFFFFu;
+    uint32_t d[8];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        int cj;
-        if constexpr (NB == 2) cj = j & 1;
-        else cj = ((j % L) + (j / L)) & 1;
-        if (cj != SEL) continue;
+    for (int k = 0; k < 8; ++k) {
+        const int j = seg_site<NB, L, SEL>(k);
         const uint32_t u = (word_of(v, j >> 2) >> (16 * ((j >> 1) & 1))) & 0xFFFFu;
-        F |= (uint32_t)(u < thi[j]) << j;
-        tie |= (uint32_t)(u == thi[j]) << j;
+        d[k] = u - thi[k];                 // borrow (bit 31) iff u < T16; 0 iff u == T16
+        F |= (d[k] >> 31) << j;
+        dmin = min(dmin, d[k]);
+    }
+    uint32_t tie = 0;
+    if (dmin == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tie |= (uint32_t)(d[k] == 0) << seg_site<NB, L, SEL>(k);
     }
     *ties = tie;
     return F;
@@ -386,16 +421,23 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
         for (int col = 0; col < 2; ++col) {
             const uint32_t ctr2 = (uint32_t)(2 * t + col);
             const uint16_t* T = Tab + (col ? ((N / 2) << NB) : 0);
+            uint4v v = philox10(0u, rr, ctr2, kTagMet, k0, k1);
 #pragma unroll 1
             for (int m = 0; m < nseg; ++m) {
                 const uint32_t D = seg[m * 64];
                 uint32_t X[NB];
                 int par;
                 gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
-                const uint4v v = philox10((uint32_t)m, rr, ctr2, kTagMet, k0, k1);
+                const gtab_ptr Tm = (gtab_ptr)(T + ((8 * m) << NB));
+                uint32_t thi[8];
+                const bool sel0 = (par ^ col) == 0;
+                if (sel0) gauss_segment_lookup<NB, L, 0>(Tm, X, thi);
+                else gauss_segment_lookup<NB, L, 1>(Tm, X, thi);
+                // the next segment's draws while the table loads are in flight
+                const uint4v vn = philox10((uint32_t)(m + 1 < nseg ? m + 1 : m), rr, ctr2, kTagMet, k0, k1);
                 uint32_t ties, F;
-                if ((par ^ col) == 0) F = gauss_segment_attempts<NB, L, 0>(T, X, v, m, &ties);
-                else F = gauss_segment_attempts<NB, L, 1>(T, X, v, m, &ties);
+                if (sel0) F = gauss_segment_decide<NB, L, 0>(thi, v, &ties);
+                else F = gauss_segment_decide<NB, L, 1>(thi, v, &ties);
                 if (ties) {
                     GaussWords xw = {};
 #pragma unroll
@@ -403,6 +445,7 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
                     F |= gauss_resolve_ties<NB>(J, Ld, N, m, xw, v, ties, beta, rr, ctr2, k0, k1);
                 }
                 seg[m * 64] = (uint16_t)(D ^ F);
+                v = vn;
             }
         }
     }
