@@ -288,12 +288,12 @@ __host__ __device__ constexpr int seg_site(int k)
     return -1;
 }
 
-// sites k and k + 4 are gathered together: their NB-bit fields must not overlap
+// sites k and k + 4 are gathered together: their (NB + 1)-bit fields must not overlap
 template <int NB, int L, int SEL>
 __host__ __device__ constexpr bool seg_pairs_ok()
 {
     for (int k = 0; k < 4; ++k)
-        if (seg_site<NB, L, SEL>(k + 4) - seg_site<NB, L, SEL>(k) < NB) return false;
+        if (seg_site<NB, L, SEL>(k + 4) - seg_site<NB, L, SEL>(k) < NB + 1) return false;
     return true;
 }
 
@@ -305,18 +305,21 @@ template <int NB, int L, int SEL>
 __device__ __forceinline__ void gauss_segment_lookup(gtab_ptr Tm, const uint32_t X[NB], uint32_t thi[8])
 {
     static_assert(seg_pairs_ok<NB, L, SEL>(), "paired sites overlap");
+    // bit a of site j's pattern goes to bit j + a + 1, so the NB + 1 bits from j are the pattern
+    // times 2: the byte offset of its u16 entry
     uint32_t P[NB];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) P[a] = X[a] << a;
+    for (int a = 0; a < NB; ++a) P[a] = X[a] << (a + 1);
+    const __attribute__((address_space(1))) uint8_t* Tb = (const __attribute__((address_space(1))) uint8_t*)Tm;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int j = seg_site<NB, L, SEL>(k), jp = seg_site<NB, L, SEL>(k + 4);
         uint32_t acc = 0;
 #pragma unroll
-        for (int a = 0; a < NB; ++a) acc |= P[a] & ((1u << (j + a)) | (1u << (jp + a)));
-        constexpr uint32_t mask = (1u << NB) - 1;
-        thi[k] = Tm[((j >> 1) << NB) + ((acc >> j) & mask)];
-        thi[k + 4] = Tm[((jp >> 1) << NB) + ((acc >> jp) & mask)];
+        for (int a = 0; a < NB; ++a) acc |= P[a] & ((2u << (j + a)) | (2u << (jp + a)));
+        constexpr uint32_t mask = (2u << NB) - 2;
+        thi[k] = *(gtab_ptr)(Tb + (((j >> 1) << NB) << 1) + ((acc >> j) & mask));
+        thi[k + 4] = *(gtab_ptr)(Tb + (((jp >> 1) << NB) << 1) + ((acc >> jp) & mask));
     }
 }
 
@@ -458,7 +461,9 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
         int par;
         gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
         const double* Jm = J + (NB == 2 ? 16 * m : 48 * m);
-#pragma unroll
+        // unrolled further, the couplings of the whole segment are held in VGPRs and the kernel
+        // drops from 5 to 4 waves per SIMD
+#pragma unroll 4
         for (int j = 0; j < 16; ++j) {
             if constexpr (NB == 2) {
                 E = E + (((X[0] >> j) & 1u) ? -Jm[j] : Jm[j]);

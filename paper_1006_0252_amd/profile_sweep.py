@@ -1,5 +1,9 @@
-"""One sweep launch (10 sweeps) per first-look regime on the L = 16 cube, R0 = 1e6, bit-packed:
-beta = 0.5, 2 and 4.  A fixed, short workload for hardware-counter passes (rocprofv3 --pmc)."""
+"""Fixed, short workloads for hardware-counter passes (rocprofv3 --pmc).
+
+default: one sweep launch (10 sweeps) per first-look regime on the L = 16 cube, R0 = 1e6,
+bit-packed: beta = 0.5, 2 and 4.
+gauss: the Gaussian ensemble's sweep, 126 runs of L = 8 at R = 2000, one launch of 100 sweeps at
+T = 2 and one at T = 0.5 (table kernel and tabled sweep)."""
 from __future__ import annotations
 
 import os
@@ -8,11 +12,30 @@ import sys
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
+def gauss():
+    import torch
+
+    from paper_1006_0252_amd import pa
+
+    specs = [dict(dim=3, L=8, R0=2000, seed=1 + i, disorder_seed=1, couplings="gauss") for i in range(126)]
+    batch = pa.Batch(specs, 3, layout="u8", device="cuda:0").init()
+    sched = pa.Schedule([0.5, 2.0], 100, batch.runs[0].n_bins, device="cuda:0")
+    batch.sweep(sched.start_sweeps())
+    batch.sweep(sched.step(1))
+    batch.stream.synchronize()
+    torch.cuda.synchronize()
+    print("ok", flush=True)
+
+
 def main():
     import numpy as np
     import torch
 
     from paper_1006_0252_amd import pa
+
+    if len(sys.argv) > 1 and sys.argv[1] == "gauss":
+        gauss()
+        return
 
     L, R0 = 16, 1_000_000
     run = pa.Run(3, L, R0, 1, 1, 4, capacity=int(np.ceil(R0 * 1.25 / 64)) * 64, layout="bits64", device="cuda:0")
