@@ -51,10 +51,11 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "stepped", "gauss"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "bias_gauss", "stepped", "gauss"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
                         "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
                         "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs); "
+                        "bias_gauss: the same on the paper's Gaussian chain (N=256, R=1000, 100 temperatures, 50 sweeps); "
                         "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work; "
                         "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
@@ -189,23 +190,32 @@ def sweep_traffic(path):
     return tr.get("bytes_per_launch")
 
 
-def bench_bias(args):
-    """Sec. IV's 1D bias measurement on the ±J ring (N = 64, R0 = 1000, 51 temperatures, 5 sweeps):
-    18 realizations x 200 runs; weighted and plain energy and free energy at beta = 5 against the
-    exact chain, bootstrap errors, and the block bias mu_k.  value = mean weighted energy bias."""
+def bench_bias(args, chain="pm1"):
+    """Sec. IV's 1D bias measurement: 18 realizations x 200 runs of a periodic chain; weighted and
+    plain energy and free energy at beta = 1, 2, 5 (nearest schedule points) against the exact chain,
+    bootstrap errors, and the block bias mu_k.  chain "pm1": the ±J ring N = 64, R0 = 1000, 51
+    temperatures, 5 sweeps; chain "gauss": the paper's Gaussian chain N = 256, R = 1000, 100
+    temperatures (19 steps evenly in beta to 0.5, 80 evenly in T to 0.2), 50 sweeps.
+    value = mean weighted -beta F_bar minus exact at beta = 5."""
     from paper_1006_0252_amd import bias
 
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    r = bias.run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), log=log)
+    cfg = bias.CHAINS[chain]
+    r = bias.run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), log=log, chain=chain)
     res = r["by_beta"]
     fb = res[5.0]["free_energy_bias_weighted"]
+    n_temps = len(cfg["betas"]())
+    steps = 18 * (n_temps - 1)
+    name = "ring_N64_bias_18x200" if chain == "pm1" else "gauss_chain_N256_bias_18x200"
     out = {
         "metric": METRIC, "value": fb[0], "unit": "weighted -beta F_bar minus exact at beta=5, mean over realizations",
-        "n_gpus": 1, "steps": 18 * 50, "warmup": 0, "ms_per_step": r["anneal_seconds"] / (18 * 50) * 1e3,
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": r["anneal_seconds"] / steps * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8+f64", "data": "synthetic",
-        "config": {"workload": "ring_N64_bias_18x200", "N": 64, "R0": 1000, "n_temps": 51, "n_sweeps": 5,
-                   "realizations": 18, "runs_per_realization": 200, "bootstrap_replicates": 100},
-        "by_beta": {str(b): {"energy_bias": {"weighted": list(v["energy_bias_weighted"]),
+        "config": {"workload": name, "N": cfg["N"], "couplings": cfg["couplings"], "R0": cfg["R0"], "n_temps": n_temps,
+                   "n_sweeps": cfg["n_sweeps"], "realizations": 18, "runs_per_realization": 200,
+                   "bootstrap_replicates": 100},
+        "by_beta": {str(b): {"beta_grid": v["beta_grid"],
+                             "energy_bias": {"weighted": list(v["energy_bias_weighted"]),
                                              "plain": list(v["energy_bias_plain"])},
                              "free_energy_bias": {"weighted": list(v["free_energy_bias_weighted"]),
                                                   "plain": list(v["free_energy_bias_plain"])},
@@ -354,6 +364,9 @@ def main():
         return
     if args.workload == "bias":
         bench_bias(args)
+        return
+    if args.workload == "bias_gauss":
+        bench_bias(args, chain="gauss")
         return
     if args.workload == "stepped":
         bench_stepped(args)

@@ -1,7 +1,10 @@
-"""Bias of weighted and unweighted averages on the ±J ring (Sec. IV, the 1D measurements).
+"""Bias of weighted and unweighted averages on the periodic chain (Sec. IV, the 1D measurements).
 
-For each disorder realization, M independent runs anneal the ring (N = 64, R0 = 1000, 51
-temperatures, 5 sweeps; one batch per realization).  At β = 5 the run free energies -βF̃_r and
+For each disorder realization, M independent runs anneal the ring (one batch per realization):
+* the ±J ring N = 64, R0 = 1000, 51 temperatures, 5 sweeps (the default); or
+* the paper's own chain: Gaussian couplings, N = 256, R = 1000, 100 temperatures (19 steps evenly
+  spaced in beta up to 0.5, then 80 evenly spaced in T down to T = 0.2), 50 sweeps
+  (`paper_schedule_1d`, `run(..., chain="gauss")`).  At β = 5 the run free energies -βF̃_r and
 energies E_r feed:
 * the weighted energy Ē and free energy -βF̄ of the whole ensemble (eqs. weight, omega, bestf), and
   the plain means, each with a bootstrap error (Sec. III; pa_bootstrap_dev);
@@ -24,16 +27,33 @@ from . import exact, pa
 REC = {n: i for i, n in enumerate(pa.RECORD_FIELDS)}
 
 
-def ring_ensemble(disorder_seed, M, R0=1000, n_temps=51, n_sweeps=5, device="cuda"):
+def paper_schedule_1d():
+    """beta = 0, 19 steps evenly spaced in beta up to 0.5, then 80 evenly spaced in T from T = 2
+    to T = 0.2: 100 temperatures (Sec. IV)."""
+    b1 = np.linspace(0.0, 0.5, 20)
+    T2 = np.linspace(2.0, 0.2, 81)[1:]
+    return np.concatenate([b1, 1.0 / T2])
+
+
+CHAINS = {
+    "pm1": dict(N=64, R0=1000, n_sweeps=5, couplings="pm1", betas=lambda: pa.linear_schedule(51)),
+    "gauss": dict(N=256, R0=1000, n_sweeps=50, couplings="gauss", betas=paper_schedule_1d),
+}
+
+
+def ring_ensemble(disorder_seed, M, R0=1000, n_temps=51, n_sweeps=5, device="cuda", N=64, couplings="pm1",
+                  betas=None):
     """M runs of one ring realization; returns (-beta F~ [M][n_temps], E mean [M][n_temps], betas,
     couplings, seconds, attempts)."""
     import torch
 
-    specs = [dict(dim=1, L=64, R0=R0, seed=100_000 * disorder_seed + r + 1, disorder_seed=disorder_seed)
-             for r in range(M)]
+    betas = pa.linear_schedule(n_temps) if betas is None else np.asarray(betas, np.float64)
+    n_temps = len(betas)
+    specs = [dict(dim=1, L=N, R0=R0, seed=100_000 * disorder_seed + r + 1, disorder_seed=disorder_seed,
+                  couplings=couplings) for r in range(M)]
     batch = pa.Batch(specs, n_temps, layout="u8", device=device)
     batch.init()
-    sched = pa.Schedule(pa.linear_schedule(n_temps), n_sweeps, batch.runs[0].n_bins, device=device)
+    sched = pa.Schedule(betas, n_sweeps, batch.runs[0].n_bins, device=device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(1, n_temps):
@@ -44,7 +64,7 @@ def ring_ensemble(disorder_seed, M, R0=1000, n_temps=51, n_sweeps=5, device="cud
     if code != pa.PA_OK:
         raise RuntimeError(f"ring ensemble failed: status {code}")
     rec = batch.records()
-    attempts = float(rec[:, 1:, REC["R"]].sum()) * 64 * n_sweeps
+    attempts = float(rec[:, 1:, REC["R"]].sum()) * N * n_sweeps
     return rec[:, :, REC["minus_betaF"]].copy(), rec[:, :, REC["E_mean"]].copy(), sched.betas, \
         batch.runs[0].couplings(), T, attempts
 
@@ -79,9 +99,11 @@ def device_bootstrap(x, A, idx, device="cuda"):
     return rep.cpu().numpy(), err.cpu().numpy()
 
 
-def run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), boot_seed=11, device="cuda", log=None):
-    """Per temperature in betas: per-realization weighted and plain estimates with bootstrap errors,
-    their means over realizations against the exact chain, and mu_k for every divisor k of M."""
+def run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), boot_seed=11, device="cuda", log=None, chain="pm1"):
+    """Per temperature in betas (the nearest of the schedule): per-realization weighted and plain
+    estimates with bootstrap errors, their means over realizations against the exact chain, and mu_k
+    for every divisor k of M."""
+    cfg = CHAINS[chain]
     ks = [k for k in range(1, M + 1) if M % k == 0]
     g = np.random.default_rng(boot_seed)
     idx = g.integers(0, M, (n_boot, M))
@@ -90,7 +112,8 @@ def run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), boot_seed=11, devic
     seconds, attempts = 0.0, 0.0
     zero = np.zeros(M)
     for d in range(1, n_real + 1):
-        X, EE, sb, J, T, att = ring_ensemble(d, M, device=device)
+        X, EE, sb, J, T, att = ring_ensemble(d, M, R0=cfg["R0"], n_sweeps=cfg["n_sweeps"], device=device, N=cfg["N"],
+                                             couplings=cfg["couplings"], betas=cfg["betas"]())
         seconds += T
         attempts += att
         for beta in betas:
@@ -102,7 +125,7 @@ def run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), boot_seed=11, devic
             # plain averages: the same device averages with equal free energies
             u = device_weighted(zero, E[:, None], 1, M, device)[0]
             _, err_u = device_bootstrap(zero, E[:, None], idx, device)
-            per[beta].append(dict(E_exact=E_ex, F_exact=F_ex, E_w=w[0], E_w_err=err[0], F_w=w[1], F_w_err=err[1],
+            per[beta].append(dict(beta_grid=float(sb[kk]), E_exact=E_ex, F_exact=F_ex, E_w=w[0], E_w_err=err[0], F_w=w[1], F_w_err=err[1],
                                   var=w[2], E_u=u[0], E_u_err=err_u[0], F_u=w[3], F_u_err=err[3]))
             for k in ks:
                 bl = device_weighted(x, E[:, None], M // k, k, device)[:, 0]
@@ -123,7 +146,7 @@ def run(n_real=18, M=200, n_boot=100, betas=(1.0, 2.0, 5.0), boot_seed=11, devic
         rows = per[beta]
         mu = {k: (float(np.mean([b[0] for b in block[beta][k]])),
                   float(np.sqrt(sum(b[1] ** 2 for b in block[beta][k])) / n_real)) for k in ks}
-        res[beta] = dict(per_realization=rows, energy_bias_weighted=agg(rows, "E_w", "E_exact", "E_w_err"),
+        res[beta] = dict(beta_grid=rows[0]["beta_grid"], per_realization=rows, energy_bias_weighted=agg(rows, "E_w", "E_exact", "E_w_err"),
                          energy_bias_plain=agg(rows, "E_u", "E_exact", "E_u_err"),
                          free_energy_bias_weighted=agg(rows, "F_w", "F_exact", "F_w_err"),
                          free_energy_bias_plain=agg(rows, "F_u", "F_exact", "F_u_err"),

@@ -71,3 +71,16 @@ def test_ring_bias_reduced():
     assert fb < 0
     mu1 = r["mu_k"][1][0]
     assert abs(mu1 - r["energy_bias_plain"][0]) < 1e-9   # blocks of one run are the plain mean
+
+
+def test_gaussian_chain_bias_reduced():
+    # the paper's 1D chain (Gaussian bonds, N = 256, R = 1000, its 100-temperature schedule, 50
+    # sweeps), 2 realizations x 40 runs: weighted estimates agree with the exact transfer-matrix
+    # values within 4 bootstrap errors at T = 0.2
+    note("gaussian chain bias, reduced")
+    r = bias.run(n_real=2, M=40, n_boot=100, betas=(5.0,), device=DEV, chain="gauss")["by_beta"][5.0]
+    assert r["beta_grid"] == 5.0
+    for p in r["per_realization"]:
+        assert abs(p["F_w"] - p["F_exact"]) < 4 * p["F_w_err"] + 0.02
+        assert abs(p["E_w"] - p["E_exact"]) < 4 * p["E_w_err"] + 0.05
+        assert p["var"] > 0

@@ -63,3 +63,29 @@ def test_ring_exact_large_chain_agrees():
         lz, e = o.ring_exact(J, beta)
         assert abs(lz - exact.ring_lnZ(J, beta)) < 1e-12 * lz
         assert abs(e - exact.ring_energy(J, beta)) < 1e-10
+
+
+@pytest.mark.parametrize("N", [6, 9, 12])
+def test_ring_exact_real_couplings_against_enumeration(N):
+    # Gaussian bonds: both exact-ring implementations against the 2^N states
+    g = np.random.default_rng(100 + N)
+    J = g.standard_normal(N)
+    states = np.array(list(itertools.product([-1, 1], repeat=N)))
+    E = (J * states * np.roll(states, -1, axis=1)).sum(axis=1)
+    for beta in (0.2, 1.0, 5.0):
+        w = np.exp(-beta * (E - E.min()))
+        lnZ = math.log(w.sum()) - beta * E.min()
+        Em = (E * w).sum() / w.sum()
+        lz, e = o.ring_exact(J, beta)
+        assert abs(lz - lnZ) < 1e-12 * abs(lnZ) + 1e-12 and abs(e - Em) < 1e-10
+        assert abs(exact.ring_lnZ(J, beta) - lnZ) < 1e-12 * abs(lnZ) + 1e-12
+        assert abs(exact.ring_energy(J, beta) - Em) < 1e-10
+
+
+def test_ring_exact_real_couplings_large_chain():
+    # N = 256 Gaussian bonds (the paper's 1D size): closed form against transfer matrices
+    J = o.couplings_gauss(1, 256, 3)
+    for beta in (0.5, 2.0, 5.0):
+        lz, e = o.ring_exact(J, beta)
+        assert abs(lz - exact.ring_lnZ(J, beta)) < 1e-12 * lz
+        assert abs(e - exact.ring_energy(J, beta)) < 1e-9 * abs(e)
