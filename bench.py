@@ -51,13 +51,14 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "bias_gauss", "stepped", "gauss"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "bias_gauss", "stepped", "gauss", "gauss_survey"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
                         "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
                         "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs); "
                         "bias_gauss: the same on the paper's Gaussian chain (N=256, R=1000, 100 temperatures, 50 sweeps); "
                         "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work; "
-                        "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs")
+                        "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs; "
+                        "gauss_survey: 25 Gaussian L=8 realizations (Var(beta F~) vs Gamma) and the worst at R=2000 and 10000")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
@@ -322,6 +323,38 @@ def bench_gauss(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_gauss_survey(args):
+    """Sec. IV's 3D study on the Gaussian L = 8 cube: 25 realizations x 100 runs (50 pairs) at
+    R = 2000 give Var(beta F~) and the pair-weighted Gamma = P(|q| < 0.2) at T = 0.2; the realization
+    with the largest Var is rerun with 126 runs at R = 2000 and at R = 10000.
+    value = Var(beta F~) at R = 2000 over Var at R = 10000 on that realization (the paper: 4.7)."""
+    from paper_1006_0252_amd import gauss3d
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    gauss3d.run(M=4, R=200, n_temps=3, n_sweeps=2)            # warm-up
+    r = gauss3d.survey(log=log)
+    rows, w = r["rows"], r["worst_runs"]
+    v = np.array([x["var_betaF"] for x in rows])
+    g = np.array([x["gamma_bar"] for x in rows])
+    secs = sum(x["seconds"] for x in rows) + sum(x["seconds"] for x in w.values())
+    att = sum(x["attempts"] for x in rows) + sum(x["attempts"] for x in w.values())
+    n_steps = 99 * (len(rows) + 2)
+    out = {
+        "metric": METRIC, "value": w[2000]["var_betaF"] / w[10000]["var_betaF"],
+        "unit": "Var(beta F~) at R=2000 / at R=10000, worst of 25 realizations", "n_gpus": 1, "steps": n_steps,
+        "warmup": 0, "ms_per_step": secs / n_steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "gauss3d_L8_survey_25x100", "L": 8, "R": 2000, "R_big": 10000, "n_temps": 100,
+                   "T": [2.0, 0.2], "n_sweeps": 100, "realizations": 25, "runs_per_realization": 100,
+                   "runs_worst": 126},
+        "realizations": rows, "worst": r["worst"], "worst_runs": {str(k): x for k, x in w.items()},
+        "var_max": float(v.max()), "var_median": float(np.median(v)),
+        "corr_var_gamma": float(np.corrcoef(v, g)[0, 1]) if g.std() > 0 else None,
+        "attempts_per_s": att / secs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -373,6 +406,9 @@ def main():
         return
     if args.workload == "gauss":
         bench_gauss(args)
+        return
+    if args.workload == "gauss_survey":
+        bench_gauss_survey(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1

@@ -74,3 +74,26 @@ def run(M=126, R=2000, L=8, n_temps=100, n_sweeps=100, disorder_seed=1, seed0=1,
                 attempts_per_sweep_step=R_per_step * L ** 3 * n_sweeps,
                 minus_betaF_bar=w["minus_betaF_bar"], var_betaF=w["var"], mean_minus_betaF=w["mean"],
                 E_bar=float(w["A_bar"][0]), gamma_bar=float(wp["A_bar"][0]), R_final=rec[:, -1, REC["R"]])
+
+
+def survey(n_real=25, M=100, R=2000, R_big=10000, M_worst=126, device="cuda:0", log=None):
+    """Sec. IV's 3D study: per realization (disorder seeds 1..n_real), M runs at R give Var(beta F~),
+    the weighted energy and the pair-weighted Gamma; the realization with the largest Var is rerun
+    with M_worst runs at R and at R_big (the paper: R = 2000 and 10000)."""
+    rows = []
+    for d in range(1, n_real + 1):
+        r = run(M=M, R=R, disorder_seed=d, seed0=1000 * d + 1, device=device)
+        rows.append(dict(disorder_seed=d, var_betaF=r["var_betaF"], gamma_bar=r["gamma_bar"], E_bar=r["E_bar"],
+                         gap=r["minus_betaF_bar"] - r["mean_minus_betaF"], seconds=r["wall_seconds"],
+                         attempts=r["attempts"]))
+        if log:
+            log(f"realization {d}: Var {r['var_betaF']:.4f} Gamma {r['gamma_bar']:.4f} E {r['E_bar']:.3f}")
+    worst = max(rows, key=lambda x: x["var_betaF"])["disorder_seed"]
+    rw = {}
+    for RR in (R, R_big):
+        r = run(M=M_worst, R=RR, disorder_seed=worst, seed0=10 ** 6 + RR, device=device)
+        rw[RR] = dict(var_betaF=r["var_betaF"], gamma_bar=r["gamma_bar"], E_bar=r["E_bar"],
+                      gap=r["minus_betaF_bar"] - r["mean_minus_betaF"], seconds=r["wall_seconds"], attempts=r["attempts"])
+        if log:
+            log(f"worst realization {worst}, R={RR}: Var {r['var_betaF']:.4f} Gamma {r['gamma_bar']:.4f} E {r['E_bar']:.3f}")
+    return dict(rows=rows, worst=worst, worst_runs=rw)
