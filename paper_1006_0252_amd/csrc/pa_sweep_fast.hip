@@ -107,6 +107,8 @@ struct PlaneCtx {
     bool valid;
 };
 
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
 // one colour of one plane z of this lane's replica
 template <int L, int LPR, int MODE, int PH>
 __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jtab, int z, int q, int col,
@@ -151,6 +153,32 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
         const int par = p0 ^ (y & 1);
         uint32_t acc = 0;
         bool tie = false;
+        if constexpr (H % 2 == 0 && MODE != 0) {
+            // sites m and m + 1 (m even) take the two 16-bit fields of one Philox word: compare
+            // both with packed 16-bit ops.  Per half: thi4 - u saturated at 0 is non-zero iff u < thi4
+            // (thi4 < 2^8 here); u - thi4 is zero iff u == thi4.  Accept bits are gathered at 2m + par
+            // (low field) and 16 + 2m + par (high field), then moved to 2m + 2 + par.
+            const u16x2 t4 = {(uint16_t)thi4, (uint16_t)thi4};
+            const u16x2 one = {1, 1};
+            u16x2 zmin = {0xFFFF, 0xFFFF};
+            uint32_t raw = 0;
+#pragma unroll
+            for (int m = 0; m < H; m += 2) {
+                const int hm = PH + y * H + m;
+                if (hm % 8 == 0 || (y == 0 && m == 0))
+                    rnd = philox10(cb + (uint32_t)(hm / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                const u16x2 w = __builtin_bit_cast(u16x2, word_of(rnd, (hm & 7) >> 1));
+                if (MODE == 2) {
+                    zmin = __builtin_elementwise_min(zmin, w);
+                } else {
+                    const u16x2 a = __builtin_elementwise_min(__builtin_elementwise_sub_sat(t4, w), one);
+                    raw |= __builtin_bit_cast(uint32_t, a) << (2 * m + par);
+                    zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t4, w));
+                }
+            }
+            tie = zmin.x == 0 || zmin.y == 0;
+            acc = (raw & 0xFFFFu) | (raw >> 14);
+        } else {
 #pragma unroll
         for (int m = 0; m < H; ++m) {
             const int hm = PH + y * H + m;  // position counted from the start of call cb
@@ -172,6 +200,7 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
                 acc |= (uint32_t)(u < thi) << xb;
                 tie |= (u == thi);
             }
+        }
         }
         uint32_t flip;
         if (MODE == 2) flip = colmask & ~c2;

@@ -226,3 +226,18 @@ def test_start_sweeps_then_steps_match_oracle():
         assert abs(run.records()[k][1] - lnQ) <= 1e-12 * max(1.0, abs(lnQ))
     s, E = run.population()
     assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+
+
+def test_ensemble_harness_small():
+    # the 3D ensemble driver on a small case: 4 runs (2 pairs), 5 temperatures from T = 2 to 0.5;
+    # its free energies are the sums of the recorded ln Q, its attempts the swept populations
+    from paper_1006_0252_amd import gauss3d
+
+    note("gauss ensemble harness, small")
+    r = gauss3d.run(M=4, R=300, n_temps=5, n_sweeps=3)
+    assert r["n_steps"] == 4 and len(r["sweep_ms"]) == 5
+    assert r["attempts"] == float(r["attempts_per_sweep_step"].sum())
+    assert r["attempts_per_sweep_step"][0] == 4 * 300 * 512 * 3
+    assert r["var_betaF"] >= 0 and np.isfinite(r["minus_betaF_bar"])
+    assert r["minus_betaF_bar"] >= r["mean_minus_betaF"] - 1e-9   # log-mean-exp >= mean
+    assert 0.0 <= r["gamma_bar"] <= 1.0

@@ -76,7 +76,7 @@ def test_init_with_host_couplings():
     assert np.array_equal(s, so) and np.array_equal(E, Eo)
 
 
-SWEEP_BETAS = [0.0, 0.35, 1.2, 5.0]
+SWEEP_BETAS = [0.0, 0.35, 1.2, 2.0, 5.0]  # regimes: 0 (beta < 1.39), 1 (1.39 .. 2.77), 2
 
 
 @pytest.mark.parametrize("dim,L,layout,R0", INIT_CASES)
