@@ -185,7 +185,8 @@ typedef struct pa_info {
  * too small L (1D: L >= 4; 3D: L >= 2, L <= 32), capacity not a positive multiple of 64, a
  * coupling kind other than PA_PM1 / PA_GAUSS, or Gaussian couplings with a layout other than
  * PA_U8.  Couplings take 1 byte per bond (PA_PM1) or 8 (PA_GAUSS), energies 4 or 8 bytes per
- * replica. */
+ * replica; with PA_GAUSS the work buffer also holds the sweep's threshold table (128 N bytes,
+ * rewritten by every pa_sweep), so buffers must be sized with the run's coupling kind. */
 int pa_buffer_sizes(int dim, int L, int layout, int couplings, int64_t capacity, int n_records, pa_sizes* out);
 
 /* Initialise runs (Sec. II: R0 replicas at beta = 0, each uniform over the 2^N states):
@@ -212,8 +213,11 @@ int pa_init_couplings(pa_run* runs, int n_runs, const int8_t* const* J_host);
  * Resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))), S = sum over consecutive blocks
  * of 256 replicas (in order) of the blocks' sums (in order), ln Q = -dbeta E_lo + ln S - ln R~,
  * copies of j ~ Poisson((R_target w_j) / S) by the ladder of pa_resample.  FP64 products and
- * sums are never fused.  Runs with Gaussian couplings are processed one after the other in
- * calls with n_runs > 1, and pa_resampled_fraction / pa_rho_steps reject them. */
+ * sums are never fused.  In calls with n_runs > 1, Gaussian runs whose pa_state blocks are
+ * consecutive and share a stream take one launch per kernel, others one after the other;
+ * pa_resampled_fraction / pa_rho_steps reject them.  pa_sweep tabulates, per call, the top 16
+ * bits of T64 for every site and neighbour pattern (cubes of side 4 and 8, chains of 16k <= 1024
+ * sites; other shapes compute dE per attempt): the accepted moves are the same. */
 
 /* theta = step->n_sweeps Metropolis sweeps of every replica at beta = step->beta_to
  * (Sec. II, the equilibration loop of the algorithm).  A sweep updates all sites of
