@@ -205,9 +205,9 @@ __device__ inline bool gauss_threshold(double h, double beta, uint64_t* T64)
     return false;
 }
 
-__device__ __forceinline__ const uint16_t* gauss_table(const pa_state* st)
+__device__ __forceinline__ uint16_t* gauss_table(const pa_state* st)
 {
-    return reinterpret_cast<const uint16_t*>(st->work + work_layout(st->N, st->n_bins, st->capacity).total);
+    return reinterpret_cast<uint16_t*>(st->work + work_layout(st->N, st->n_bins, st->capacity).total);
 }
 
 // grid (entries / 256, runs): entry e = (c, h, b) of run blockIdx.y
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ stat
     uint64_t T64 = 0;
     const bool always = gauss_threshold(gauss_field_pattern<NB>(reinterpret_cast<const double*>(st->J), i, b, L, N),
                                         beta, &T64);
-    const_cast<uint16_t*>(gauss_table(st))[e] = always ? (uint16_t)0xFFFFu : (uint16_t)(T64 >> 48);
+    gauss_table(st)[e] = always ? (uint16_t)0xFFFFu : (uint16_t)(T64 >> 48);
 }
 
 __device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t w)  // bytes b0..b3 in {0,1} -> b0 | b1<<1 | ...
