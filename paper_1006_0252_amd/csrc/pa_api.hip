@@ -157,6 +157,11 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step)
         if (st != PA_OK) return st;
         return hip_status(hipGetLastError());
     }
+    if (batchable(runs, n_runs) && runs[0].dim == 1 && n_runs <= 65535) {
+        bool same = true;
+        for (int r = 1; r < n_runs; ++r) same = same && runs[r].L == runs[0].L;
+        if (same) return launch_sweep_chain_batch(runs, n_runs, *step, (hipStream_t)runs[0].stream);
+    }
     bool all_gauss = true, consecutive = true;
     for (int r = 0; r < n_runs; ++r) {
         all_gauss = all_gauss && runs[r].couplings == PA_GAUSS;

@@ -264,11 +264,13 @@ __global__ void __launch_bounds__(256) k_sweep3(const pa_state* __restrict__ st,
 }
 
 // ---------------------------------------------------------------- 1D kernel (ring)
-// rows of 32 sites; row rho holds sites 32 rho .. 32 rho + len - 1
+// rows of 32 sites; row rho holds sites 32 rho .. 32 rho + len - 1; grid.y = run (consecutive
+// states of one chain length and layout)
 template <int LAYOUT, int LPR, bool ZEROT>
-__global__ void __launch_bounds__(256) k_sweep1(const pa_state* __restrict__ st, SweepParams p, int NRr)
+__global__ void __launch_bounds__(256) k_sweep1(const pa_state* __restrict__ base, SweepParams p, int NRr)
 {
     constexpr int RPW = 64 / LPR;
+    const pa_state* __restrict__ st = base + blockIdx.y;
     if (st->status) return;  // sticky error: the population stays as it is
     extern __shared__ uint32_t lds[];
     const int N = st->N;
@@ -441,7 +443,7 @@ static int launch3(const pa_run& run, const SweepParams& p, SweepConfig cfg, boo
 }
 
 template <int LAYOUT, int LPR, bool Z>
-static int launch1_t(const pa_run& run, const SweepParams& p, int wpb, hipStream_t s)
+static int launch1_t(const pa_run& run, const SweepParams& p, int wpb, hipStream_t s, int n_runs, int64_t capacity)
 {
     const int N = run.L;
     const int NR = (N + 31) / 32;
@@ -456,21 +458,26 @@ static int launch1_t(const pa_run& run, const SweepParams& p, int wpb, hipStream
     }
     if (lds > limit) return PA_ERR_ARG;
     const int64_t per_block = (int64_t)wpb * RPW;
-    const int64_t blocks = (run.capacity + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_sweep1<LAYOUT, LPR, Z>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, run.state, p, NR);
+    const int64_t blocks = (capacity + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_sweep1<LAYOUT, LPR, Z>), dim3((unsigned)blocks, (unsigned)n_runs), dim3(64 * wpb), lds, s,
+                       run.state, p, NR);
     return PA_OK;
 }
 
-static int launch1(const pa_run& run, const SweepParams& p, SweepConfig cfg, bool zero, hipStream_t s)
+static int launch1(const pa_run& run, const SweepParams& p, SweepConfig cfg, bool zero, hipStream_t s, int n_runs = 1,
+                   int64_t capacity = 0)
 {
+    const int64_t cap = capacity > 0 ? capacity : run.capacity;  // the largest of the runs
     if (run.layout == PA_U8) {
-        if (cfg.lpr == 2) return zero ? launch1_t<kLayoutU8, 2, true>(run, p, cfg.wpb, s)
-                                      : launch1_t<kLayoutU8, 2, false>(run, p, cfg.wpb, s);
-        return zero ? launch1_t<kLayoutU8, 1, true>(run, p, cfg.wpb, s) : launch1_t<kLayoutU8, 1, false>(run, p, cfg.wpb, s);
+        if (cfg.lpr == 2) return zero ? launch1_t<kLayoutU8, 2, true>(run, p, cfg.wpb, s, n_runs, cap)
+                                      : launch1_t<kLayoutU8, 2, false>(run, p, cfg.wpb, s, n_runs, cap);
+        return zero ? launch1_t<kLayoutU8, 1, true>(run, p, cfg.wpb, s, n_runs, cap)
+                    : launch1_t<kLayoutU8, 1, false>(run, p, cfg.wpb, s, n_runs, cap);
     }
-    if (cfg.lpr == 2) return zero ? launch1_t<kLayoutBits, 2, true>(run, p, cfg.wpb, s)
-                                  : launch1_t<kLayoutBits, 2, false>(run, p, cfg.wpb, s);
-    return zero ? launch1_t<kLayoutBits, 1, true>(run, p, cfg.wpb, s) : launch1_t<kLayoutBits, 1, false>(run, p, cfg.wpb, s);
+    if (cfg.lpr == 2) return zero ? launch1_t<kLayoutBits, 2, true>(run, p, cfg.wpb, s, n_runs, cap)
+                                  : launch1_t<kLayoutBits, 2, false>(run, p, cfg.wpb, s, n_runs, cap);
+    return zero ? launch1_t<kLayoutBits, 1, true>(run, p, cfg.wpb, s, n_runs, cap)
+                : launch1_t<kLayoutBits, 1, false>(run, p, cfg.wpb, s, n_runs, cap);
 }
 
 // default launch shape per lattice (lanes per replica, waves per block)
@@ -549,6 +556,24 @@ int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
             default: return PA_ERR_ARG;
         }
     }
+    if (st != PA_OK) return st;
+    return hip_status(hipGetLastError());
+}
+
+// n > 1 chain runs with consecutive states, one length and layout: one launch, grid.y = run
+int launch_sweep_chain_batch(const pa_run* runs, int n, const pa_step& step, hipStream_t s)
+{
+    SweepParams p;
+    build_sweep_params(step, 2, &p);
+    const bool zero = p.thi[2] == 0;
+    SweepConfig cfg = default_config(1, runs[0].L);
+    if (g_override.lpr) cfg = g_override;
+    const int NR = (runs[0].L + 31) / 32;
+    if (cfg.lpr > NR) cfg.lpr = 1;
+    if (cfg.lpr > 2) cfg.lpr = 2;
+    int64_t cap = 0;
+    for (int r = 0; r < n; ++r) cap = runs[r].capacity > cap ? runs[r].capacity : cap;
+    const int st = launch1(runs[0], p, cfg, zero, s, n, cap);
     if (st != PA_OK) return st;
     return hip_status(hipGetLastError());
 }

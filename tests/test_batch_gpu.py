@@ -234,3 +234,26 @@ def test_full_batched_configuration_sampled_parity():
         c, off = b.runs[i].counts_offsets(sp["R0"])
         assert np.array_equal(c, counts_o), f"copy numbers of run {i}"
         assert b.runs[i].records()[2][3] == S_o
+
+
+@pytest.mark.parametrize("layout,N", [("u8", 64), ("bits64", 64), ("u8", 100), ("bits64", 100)])
+def test_chain_batch_matches_oracle(layout, N):
+    # chains of one length sweep in one launch (grid row = run): each run against the oracle
+    note(f"chain batch {layout} N={N}")
+    R0s = (300, 77, 1000, 130)
+    nT, ns = 7, 3
+    betas = [5.0 * k / (nT - 1) for k in range(nT)]
+    specs = [dict(dim=1, L=N, R0=R0, seed=60 + i, disorder_seed=2 + (i & 1)) for i, R0 in enumerate(R0s)]
+    batch = pa.Batch(specs, nT, layout=layout, device=DEV).init()
+    sched = pa.Schedule(betas, ns, batch.runs[0].n_bins, device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k)
+    code, flags = batch.status()
+    assert code == pa.PA_OK and not flags.any()
+    for sp, run in zip(specs, batch.runs):
+        J = o.couplings(1, N, sp["disorder_seed"])
+        st_o, rec_o, s_o, E_o = o.run(1, N, J, sp["seed"], sp["R0"], betas, ns, capacity=run.capacity)
+        assert st_o == 0
+        s, E = run.population()
+        assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+        assert np.array_equal(run.records()[:, 4], rec_o[:, 1])
