@@ -51,14 +51,16 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU work of the oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "sweep_L16_R1e6_traffic.json"))
-    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "bias_gauss", "stepped", "gauss", "gauss_survey"],
+    p.add_argument("--workload", default="L16", choices=["L16", "batched", "learned", "bias", "bias_gauss", "stepped", "gauss", "gauss_survey",
+                            "gauss_stepped"],
                    help="L16: the throughput configuration (default); batched: 256 runs in one graph; "
                         "learned: learned vs fixed schedules, wall time to Var(beta F~) <= 1e-3 at L=12; "
                         "bias: weighted vs plain averages against the exact ring (18 realizations x 200 runs); "
                         "bias_gauss: the same on the paper's Gaussian chain (N=256, R=1000, 100 temperatures, 50 sweeps); "
                         "stepped: Var(beta F~(beta)) for constant, stepped and learned schedules at equal work; "
                         "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs; "
-                        "gauss_survey: 25 Gaussian L=8 realizations (Var(beta F~) vs Gamma) and the worst at R=2000 and 10000")
+                        "gauss_survey: 25 Gaussian L=8 realizations (Var(beta F~) vs Gamma) and the worst at R=2000 and 10000; "
+                        "gauss_stepped: constant R=2000 vs R_beta 1000/3000 (beta_c=0.9) on the worst Gaussian realization")
     p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
     return p.parse_args()
 
@@ -355,6 +357,40 @@ def bench_gauss_survey(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_gauss_stepped(args):
+    """Sec. IV's population size stepped with temperature, on the Gaussian L = 8 cube: the realization
+    with the largest Var(beta F~) of the 25 of gauss_survey (disorder seed 10), 250 runs each with
+    R_beta = 2000 throughout and with R_beta = 1000 for beta < 0.9, 3000 from beta = 0.9 on (nearly
+    equal work); 100 temperatures from T = 2 to 0.2, 100 sweeps.  value = Var(beta F~) at T = 0.2,
+    constant over stepped (the paper: 0.57 / 0.36)."""
+    from paper_1006_0252_amd import gauss3d
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    gauss3d.run(M=4, R=200, n_temps=3, n_sweeps=2)            # warm-up
+    betas = gauss3d.schedule()
+    out_s = {}
+    for name, Rt in (("constant", np.full(len(betas), 2000.0)), ("stepped", np.where(betas < 0.9, 1000.0, 3000.0))):
+        r = gauss3d.run(M=250, disorder_seed=10, seed0=20_000 + (0 if name == "constant" else 1000), R_targets=Rt)
+        vp = r["var_profile"]
+        out_s[name] = {"R_targets": {"beta<0.9": float(Rt[0]), "beta>=0.9": float(Rt[-1])}, "attempts": r["attempts"],
+                       "seconds": r["wall_seconds"], "var_beta5": float(vp[-1]), "E_bar": r["E_bar"],
+                       "minus_betaF_bar": r["minus_betaF_bar"],
+                       "var_at": {f"{b:.3f}": float(vp[int(np.argmin(np.abs(betas[1:] - b)))]) for b in (0.9, 1.5, 2.0, 3.0, 4.0, 5.0)}}
+        log(f"{name}: Var(beta=5) {vp[-1]:.4f}, attempts {r['attempts']:.3e}, E {r['E_bar']:.3f}")
+    c, st = out_s["constant"], out_s["stepped"]
+    n_steps = 2 * (len(betas) - 1)
+    out = {
+        "metric": METRIC, "value": c["var_beta5"] / st["var_beta5"],
+        "unit": "Var(beta F~) at T=0.2, constant R / stepped R_beta (equal work)", "n_gpus": 1, "steps": n_steps,
+        "warmup": 0, "ms_per_step": (c["seconds"] + st["seconds"]) / n_steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "gauss3d_L8_stepped_R_worst", "L": 8, "disorder_seed": 10, "runs": 250, "n_temps": 100,
+                   "T": [2.0, 0.2], "n_sweeps": 100, "beta_c": 0.9},
+        "schedules": out_s, "work_ratio": st["attempts"] / c["attempts"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -409,6 +445,9 @@ def main():
         return
     if args.workload == "gauss_survey":
         bench_gauss_survey(args)
+        return
+    if args.workload == "gauss_stepped":
+        bench_gauss_stepped(args)
         return
     dev = "cuda:0"
     n_steps = args.n_temps - 1

@@ -29,15 +29,21 @@ def schedule(n_temps=100, T_hi=2.0, T_lo=0.2):
     return 1.0 / np.linspace(T_hi, T_lo, n_temps)
 
 
-def run(M=126, R=2000, L=8, n_temps=100, n_sweeps=100, disorder_seed=1, seed0=1, device="cuda:0", log=None):
+def run(M=126, R=2000, L=8, n_temps=100, n_sweeps=100, disorder_seed=1, seed0=1, device="cuda:0", log=None,
+        R_targets=None):
+    """M runs of one realization; R_targets (per temperature, optional) makes the population size
+    follow the temperature (Sec. IV: R_beta), the random start then has R_targets[0] replicas."""
     import torch
 
     betas = schedule(n_temps)
     nT = len(betas)
-    specs = [dict(dim=3, L=L, R0=R, seed=seed0 + i, disorder_seed=disorder_seed, couplings="gauss") for i in range(M)]
-    batch = pa.Batch(specs, nT, layout="u8", device=device)
+    Rt = None if R_targets is None else np.asarray(R_targets, np.float64)
+    R0 = R if Rt is None else int(Rt[0])
+    cf = 1.25 if Rt is None else 1.25 * float(Rt.max()) / R0
+    specs = [dict(dim=3, L=L, R0=R0, seed=seed0 + i, disorder_seed=disorder_seed, couplings="gauss") for i in range(M)]
+    batch = pa.Batch(specs, nT, layout="u8", device=device, capacity_factor=cf)
     batch.init()
-    sched = pa.Schedule(betas, n_sweeps, batch.runs[0].n_bins, device=device)
+    sched = pa.Schedule(betas, n_sweeps, batch.runs[0].n_bins, device=device, R_targets=Rt)
     s = batch.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(1, nT)]
     torch.cuda.synchronize()
@@ -62,7 +68,7 @@ def run(M=126, R=2000, L=8, n_temps=100, n_sweeps=100, disorder_seed=1, seed0=1,
         raise RuntimeError(f"gaussian ensemble failed: status {code}, runs {np.nonzero(flags)[0].tolist()}")
     sweep_ms = np.array([ev0[0].elapsed_time(ev0[1])] + [a.elapsed_time(b) for a, b in ev])
     rec = batch.records()                                        # [M][nT][13]
-    R_per_step = np.concatenate([[float(R * M)], rec[:, 1:, REC["R"]].sum(axis=0)])  # replicas swept per block
+    R_per_step = np.concatenate([[float(R0 * M)], rec[:, 1:, REC["R"]].sum(axis=0)])  # replicas swept per block
     attempts = float(R_per_step.sum()) * L ** 3 * n_sweeps
     x = rec[:, 1:, REC["lnQ"]].sum(axis=1)                      # -beta_0 F~ relative to T = 2
     E = rec[:, -1, REC["E_mean"]]
@@ -70,7 +76,10 @@ def run(M=126, R=2000, L=8, n_temps=100, n_sweeps=100, disorder_seed=1, seed0=1,
     xp = x[0::2] + x[1::2]
     gam = rec[0::2, -1, REC["gamma"]]
     wp = pa.weighted_average(xp, gam[:, None])
-    return dict(betas=betas, n_steps=nT - 1, wall_seconds=wall, sweep_ms=sweep_ms, attempts=attempts,
+    # Var(beta F~(beta_k)) over the runs at every temperature (relative to T = 2, as above)
+    xk = np.cumsum(rec[:, 1:, REC["lnQ"]], axis=1)
+    var_profile = np.array([pa.weighted_average(xk[:, k])["var"] for k in range(nT - 1)])
+    return dict(betas=betas, n_steps=nT - 1, wall_seconds=wall, var_profile=var_profile, sweep_ms=sweep_ms, attempts=attempts,
                 attempts_per_sweep_step=R_per_step * L ** 3 * n_sweeps,
                 minus_betaF_bar=w["minus_betaF_bar"], var_betaF=w["var"], mean_minus_betaF=w["mean"],
                 E_bar=float(w["A_bar"][0]), gamma_bar=float(wp["A_bar"][0]), R_final=rec[:, -1, REC["R"]])

@@ -241,3 +241,16 @@ def test_ensemble_harness_small():
     assert r["var_betaF"] >= 0 and np.isfinite(r["minus_betaF_bar"])
     assert r["minus_betaF_bar"] >= r["mean_minus_betaF"] - 1e-9   # log-mean-exp >= mean
     assert 0.0 <= r["gamma_bar"] <= 1.0
+
+
+def test_ensemble_harness_stepped_targets():
+    # R_beta stepped up at the third temperature: the start has R_targets[0] replicas, the work
+    # counts the swept populations, and the populations follow the new target
+    from paper_1006_0252_amd import gauss3d
+
+    note("gauss ensemble harness, stepped targets")
+    Rt = [200.0, 200.0, 600.0, 600.0, 600.0]
+    r = gauss3d.run(M=4, n_temps=5, n_sweeps=2, R_targets=Rt)
+    assert r["attempts_per_sweep_step"][0] == 4 * 200 * 512 * 2
+    assert np.all(np.abs(r["R_final"] - 600) < 6 * np.sqrt(600))
+    assert len(r["var_profile"]) == 4 and np.all(r["var_profile"] >= 0)
