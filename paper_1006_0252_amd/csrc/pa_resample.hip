@@ -474,7 +474,10 @@ int launch_hist(const pa_run* runs, int n, hipStream_t s)
 {
     const BatchShape b = batch_shape(runs, n);
     const size_t hist_lds = b.bins_max <= 16384 ? (size_t)b.bins_max * 4 : 0;
-    const unsigned hist_blocks = (unsigned)std::min<int64_t>(1024, (b.cap_max + 255) / 256);
+    // few blocks: each block zeroes and scans all bins of its LDS histogram and merges the occupied
+    // ones with global atomics that land on the same few bins (L = 16, 1e6 replicas: 1024 blocks
+    // 98 us, 256 blocks 29 us, 128 blocks 21 us)
+    const unsigned hist_blocks = (unsigned)std::min<int64_t>(128, (b.cap_max + 255) / 256);
     hipLaunchKernelGGL(k_hist_clear, dim3(32, n), dim3(256), 0, s, runs[0].state);
     hipLaunchKernelGGL(k_hist, dim3(hist_blocks, n), dim3(256), hist_lds, s, runs[0].state);
     return PA_OK;
