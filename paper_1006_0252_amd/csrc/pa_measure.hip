@@ -117,15 +117,19 @@ __global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_s
 }
 
 // q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A
-__global__ void k_overlap_stats(pa_state* base, const pa_state* b_given, int pair_xor)
+// one block per run: strided partial sums over the overlap histogram, then a fixed-order tree
+// reduction (P and the Gamma count are integers and exact; q2 and q4 differ from a serial sum only
+// in rounding order)
+__global__ void __launch_bounds__(256) k_overlap_stats(pa_state* base, const pa_state* b_given, int pair_xor)
 {
     pa_state* a = base + blockIdx.y;
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
+    __shared__ double red[4][256];
     const int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
     const int N = a->N;
     double P = 0.0, q2 = 0.0, q4 = 0.0, g = 0.0;
-    for (int d = 0; d <= N; ++d) {
+    for (int d = threadIdx.x; d <= N; d += blockDim.x) {
         const double c = (double)qh[d];
         const double q = (double)(N - 2 * d) / (double)N;
         P += c;
@@ -133,11 +137,23 @@ __global__ void k_overlap_stats(pa_state* base, const pa_state* b_given, int pai
         q4 += c * q * q * q * q;
         if (fabs(q) < 0.2) g += c;
     }
-    pa_record* rec = a->record + a->k;
-    rec->q2 = q2 / P;
-    rec->q4 = q4 / P;
-    rec->gamma = g / P;
-    rec->n_pairs = P;
+    red[0][threadIdx.x] = P;
+    red[1][threadIdx.x] = q2;
+    red[2][threadIdx.x] = q4;
+    red[3][threadIdx.x] = g;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pa_record* rec = a->record + a->k;
+        rec->q2 = red[1][0] / red[0][0];
+        rec->q4 = red[2][0] / red[0][0];
+        rec->gamma = red[3][0] / red[0][0];
+        rec->n_pairs = red[0][0];
+    }
 }
 
 __global__ void k_free_energy(const pa_state* __restrict__ base, int n, double* out)
@@ -169,7 +185,7 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
         else
             hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + 255) / 256), n), dim3(256), 0, s, base, bg,
                                pair_xor);
-        hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(1), 0, s, base, bg, pair_xor);
+        hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(256), 0, s, base, bg, pair_xor);
     }
     return hip_status(hipGetLastError());
 }
@@ -189,7 +205,7 @@ int launch_measure_gauss(const pa_run* runs, int n, const pa_run* partner, int p
     const pa_state* bg = partner ? partner->state : nullptr;
     hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), n), dim3(256), 0, s, base);
     hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
-    hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(1), 0, s, base, bg, pair_xor);
+    hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(256), 0, s, base, bg, pair_xor);
     return hip_status(hipGetLastError());
 }
 
