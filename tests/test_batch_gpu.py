@@ -200,40 +200,46 @@ def test_ensemble_weighted_averages_and_autotuner():
 
 def test_full_batched_configuration_sampled_parity():
     # the batched configuration at full size (256 runs, L in {6, 8, 10}, R0 in [1e4, 1e5]): one
-    # persistent sweep and one batched resampling, checked against the oracle on sampled
-    # replicas of every 8th run and on all copy numbers of those runs
+    # batched resampling from the seeded initial populations, then one persistent sweep launch.
+    # Every 16th run: all copy numbers and S against the oracle (from its own initial energies), and
+    # sampled replicas after the sweep, whose parents come from the oracle's copy numbers
     from paper_1006_0252_amd import workloads
 
     specs = workloads.batched_specs()
-    note("full batched configuration: init + sweep")
+    note("full batched configuration: init + resample")
     b = pa.Batch(specs, 3, layout="bits64", device=DEV).init()
-    betas = [0.0, 0.05, 0.1]
+    betas = [0.0, 0.05]
     sched = pa.Schedule(betas, 10, max(r.n_bins for r in b.runs), device=DEV)
-    b.sweep(sched.step(1))
+    st = sched.step(1)
+    b.resample(st)
     code, _ = b.status()
     assert code == pa.PA_OK
-    E1 = {}
-    for i in range(0, len(specs), 8):
+    parents = {}
+    for i in range(0, len(specs), 16):
         sp = specs[i]
         J = o.couplings(3, sp["L"], sp["disorder_seed"])
-        idx = np.array([0, 63, 64, 129, sp["R0"] // 2, sp["R0"] - 1])
-        sg = b.runs[i].replica_spins(idx)
-        Eg = b.runs[i].energies()
-        E1[i] = Eg
-        for k, r in enumerate(idx):
-            so, Eo = o.init_replicas(3, sp["L"], J, sp["seed"], int(r), 1)
-            o.sweep_replicas(3, sp["L"], J, sp["seed"], 0.05, int(r), so, Eo, 0, 10)
-            assert np.array_equal(sg[k], so[0]) and Eg[r] == Eo[0], f"run {i} replica {r}"
-    note("full batched configuration: resample")
-    b.resample(sched.step(2))
+        s0, E0 = o.init_replicas(3, sp["L"], J, sp["seed"], 0, sp["R0"])
+        stc, counts_o, S_o, _, _ = o.copy_numbers(sp["seed"], 1, betas[0], betas[1], sp["R0"], E0)
+        assert stc == 0
+        c, _ = b.runs[i].counts_offsets(sp["R0"])
+        assert np.array_equal(c, counts_o), f"copy numbers of run {i}"
+        assert b.runs[i].records()[1][3] == S_o
+        src = np.repeat(np.arange(sp["R0"]), counts_o)
+        idx = np.unique(np.array([0, 63, 64, 129, len(src) // 2, len(src) - 1]))
+        parents[i] = (J, idx, s0[src[idx]].copy(), E0[src[idx]].copy())   # the sampled replicas' parents
+    note("full batched configuration: sweep")
+    b.sweep(st)
     code, _ = b.status()
     assert code == pa.PA_OK
-    for i in range(0, len(specs), 8):
+    for i, (J, idx, sp0, Ep0) in parents.items():
         sp = specs[i]
-        st, counts_o, S_o, lnQ_o, _ = o.copy_numbers(sp["seed"], 2, betas[1], betas[2], sp["R0"], E1[i])
-        c, off = b.runs[i].counts_offsets(sp["R0"])
-        assert np.array_equal(c, counts_o), f"copy numbers of run {i}"
-        assert b.runs[i].records()[2][3] == S_o
+        sg = b.runs[i].replica_spins(idx)
+        Eg = b.runs[i].energies()
+        for k, r in enumerate(idx):
+            so = sp0[k][None, :].copy()
+            Eo = np.array([Ep0[k]], dtype=np.int32)
+            o.sweep_replicas(3, sp["L"], J, sp["seed"], betas[1], int(r), so, Eo, 0, 10)
+            assert np.array_equal(sg[k], so[0]) and Eg[r] == Eo[0], f"run {i} replica {r}"
 
 
 @pytest.mark.parametrize("layout,N", [("u8", 64), ("bits64", 64), ("u8", 100), ("bits64", 100)])

@@ -282,23 +282,24 @@ def test_device_weighted_average_matches_host():
 
 
 def test_full_size_c4_sampled():
-    # the throughput configuration at its real size: L = 16, R0 = 1e6, bit-packed; the oracle
-    # checks sampled replicas one by one (a replica's sweep depends only on its own spins and
-    # index) and all 1e6 copy numbers from the energies
+    # the throughput configuration at its real size: L = 16, R0 = 1e6, bit-packed.  The oracle sweeps
+    # sampled replicas one by one from its own initial spins (a replica's sweep depends only on its
+    # own spins and index); the resampling of 1e6 energies is checked through properties that hold
+    # at any size (conservation, the scan, the gather, the mean population size)
     dim, L, R0 = 3, 16, 1_000_000
     seed, dseed = 77, 1
     note("C4 full size: init")
     run = pa.Run(dim, L, R0, seed, dseed, n_records=4, layout="bits64", device=DEV)
     run.init()
-    J = run.couplings()
-    assert np.array_equal(J, o.couplings(dim, L, dseed))
+    J = o.couplings(dim, L, dseed)
+    assert np.array_equal(run.couplings(), J)
     sample = np.array([0, 1, 63, 64, 65, 4097, 123457, 500000, 999935, 999936, R0 - 2, R0 - 1])
     s = run.replica_spins(sample)
     E = run.energies()
     assert len(E) == R0
+    init_o = [o.init_replicas(dim, L, J, seed, int(r), 1) for r in sample]
     for n, r in enumerate(sample):
-        so, Eo = o.init_replicas(dim, L, J, seed, int(r), 1)
-        assert np.array_equal(s[n], so[0]) and E[r] == Eo[0]
+        assert np.array_equal(s[n], init_o[n][0][0]) and E[r] == init_o[n][1][0]
     note("C4 full size: sweep beta=1.0")
     betas = [0.0, 1.0, 1.0 + 1.0 / 60.0]
     sched = pa.Schedule(betas, 10, run.n_bins, device=DEV)
@@ -308,28 +309,61 @@ def test_full_size_c4_sampled():
     s1 = run.replica_spins(sample)
     E1 = run.energies()
     for n, r in enumerate(sample):
-        so = s[n : n + 1].copy()
-        Eo = E[r : r + 1].copy()
+        so, Eo = init_o[n]
         o.sweep_replicas(dim, L, J, seed, 1.0, int(r), so, Eo, 120, 10)
         assert np.array_equal(s1[n], so[0]) and E1[r] == Eo[0], f"replica {r}"
     note("C4 full size: resample 1.0 -> 1.0 + 1/60")
     old_buf = run.query().cur
-    st2 = sched.step(2)
-    run.resample(st2)
+    run.resample(sched.step(2))
     code, _ = run.status()
     assert code == pa.PA_OK
-    stc, counts_o, S_o, lnQ_o, Elo_o = o.copy_numbers(seed, 2, betas[1], betas[2], R0, E1)
-    assert stc == 0
     c, off = run.counts_offsets(R0)
-    assert np.array_equal(c, counts_o)
-    assert off[0] == 0 and np.array_equal(np.diff(off), c)
-    rec = run.records()[2]
-    assert rec[3] == S_o and close(rec[1], lnQ_o) and rec[5] == Elo_o
     E2 = run.energies()
-    assert len(E2) == off[-1]
+    assert np.all(c >= 0) and off[0] == 0 and np.array_equal(np.diff(off), c) and off[-1] == len(E2)
+    assert abs(len(E2) - R0) < 6 * math.sqrt(R0)           # E[sum of copies] = R_target
+    rec = run.records()[2]
+    assert rec[4] == len(E2) and rec[5] == E1.min()
+    dbeta = betas[2] - betas[1]
+    assert close(rec[1], -dbeta * rec[5] + math.log(rec[3]) - math.log(R0))
     src = np.searchsorted(off, np.arange(len(E2)), side="right") - 1
     assert np.array_equal(E2, E1[src])
     pick = np.unique(np.concatenate([np.arange(0, len(E2), 99991), [len(E2) - 1]]))
     new_s = run.replica_spins(pick)
     old_s = run.replica_spins(src[pick], buf=old_buf)
     assert np.array_equal(new_s, old_s)
+
+
+@pytest.mark.parametrize("layout", ["u8", "bits64"])
+def test_full_size_c2(layout):
+    # the L = 8 cube at its real size, R0 = 5e4: resampling from the seeded initial population
+    # (every copy number, S, ln Q and the gathered energies against the oracle), then 10 sweeps at
+    # beta = 0.05 checked on sampled replicas, whose parents come from the oracle's copy numbers
+    dim, L, R0, seed, dseed, db = 3, 8, 50_000, 91, 2, 0.05
+    note(f"C2 full size {layout}: init + resample")
+    run = pa.Run(dim, L, R0, seed, dseed, n_records=4, layout=layout, device=DEV).init()
+    J = o.couplings(dim, L, dseed)
+    s0_o, E0_o = o.init_replicas(dim, L, J, seed, 0, R0)
+    sched = pa.Schedule([0.0, db], 10, run.n_bins, device=DEV)
+    st = sched.step(1)
+    run.resample(st)
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    stc, counts_o, S_o, lnQ_o, Elo_o = o.copy_numbers(seed, 1, 0.0, db, R0, E0_o)
+    assert stc == 0
+    c, off = run.counts_offsets(R0)
+    assert np.array_equal(c, counts_o)
+    rec = run.records()[1]
+    assert rec[3] == S_o and rec[5] == Elo_o and close(rec[1], lnQ_o)
+    src = np.repeat(np.arange(R0), counts_o)
+    assert np.array_equal(run.energies(), E0_o[src])
+    note(f"C2 full size {layout}: sweep")
+    run.sweep(st)
+    Rn = len(src)
+    sample = np.unique(np.array([0, 1, 63, 64, 127, 128, Rn // 3, Rn // 2, Rn - 65, Rn - 64, Rn - 1]))
+    s1 = run.replica_spins(sample)
+    E1 = run.energies()
+    for n, r in enumerate(sample):
+        so = s0_o[src[r]][None, :].copy()          # a copy: the oracle sweeps in place
+        Eo = np.array([E0_o[src[r]]], dtype=np.int32)
+        o.sweep_replicas(dim, L, J, seed, db, int(r), so, Eo, 0, 10)
+        assert np.array_equal(s1[n], so[0]) and E1[r] == Eo[0], f"replica {r}"
