@@ -67,19 +67,31 @@ struct FastLayout {
     static constexpr int JPAD = LPR == 4 ? 4 : 0;
     static constexpr int JSTRIDE = L * 8 + JPAD;                // dwords of coupling masks per plane
     static constexpr int JDWORDS = L * JSTRIDE;
+    static constexpr int TDWORDS = 16;                          // pair-threshold table after the masks
+    static constexpr int TAB_DWORDS = JDWORDS + TDWORDS;        // block-shared tables
     static constexpr int ROW_BYTES = L * PSTRIDE * 2;           // one wave's rows
-    static constexpr size_t lds_bytes(int wpb) { return (size_t)JDWORDS * 4 + (size_t)wpb * ROW_BYTES; }
+    static constexpr size_t lds_bytes(int wpb) { return (size_t)TAB_DWORDS * 4 + (size_t)wpb * ROW_BYTES; }
 };
 
 // lanes per replica used for each lattice size (L = 2 mod 4 needs one lane per replica so
 // that the Philox phase of a plane is uniform over the wave)
 __host__ __device__ constexpr int batch_lpr(int L) { return L % 4 != 0 ? 1 : (L >= 12 ? 4 : (L >= 8 ? 2 : 1)); }
 
-// coupling masks per row, entries +x, +y, +z, -x, -y, -z bonds with J = -1
+// coupling masks per row, entries +x, +y, +z, -x, -y, -z bonds with J = -1; then the
+// thresholds of two consecutive sites of a colour by their class bits: entry
+// a + 4 b (a, b = c0 + 2 c1 of the first and second site) holds thi(a) | thi(b) << 16, with
+// class index 0, 1, 2 for c = 4, 5, 6 (3 cannot occur at a candidate site).  A threshold of
+// 0x10000 (always accept) is stored as 0xFFFF: every u below it accepts, and u = 0xFFFF equals
+// it, which flags a tie that the exact path settles with the true threshold
 template <int L, int LPR>
-__device__ void build_jtab(const pa_state* st, uint32_t* jtab, int tid, int nthr)
+__device__ void build_jtab(const pa_state* st, uint32_t* jtab, const FastThr& th, int tid, int nthr)
 {
     using F = FastLayout<L, LPR>;
+    if (tid < F::TDWORDS) {
+        const uint32_t t[4] = {min(th.thi4, 0xFFFFu), min(th.thi5, 0xFFFFu), min(th.thi6, 0xFFFFu),
+                               min(th.thi6, 0xFFFFu)};
+        jtab[F::JDWORDS + tid] = t[tid & 3] | (t[tid >> 2] << 16);
+    }
     const int8_t* J = st->J;
     for (int rho = tid; rho < F::NR; rho += nthr) {
         const int y = rho % L, z = rho / L;
@@ -153,15 +165,21 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
         const int par = p0 ^ (y & 1);
         uint32_t acc = 0;
         bool tie = false;
-        if constexpr (H % 2 == 0 && MODE != 0) {
+        if constexpr (H % 2 == 0) {
             // sites m and m + 1 (m even) take the two 16-bit fields of one Philox word: compare
-            // both with packed 16-bit ops.  Per half: thi4 - u saturated at 0 is non-zero iff u < thi4
-            // (thi4 < 2^8 here); u - thi4 is zero iff u == thi4.  Accept bits are gathered at 2m + par
-            // (low field) and 16 + 2m + par (high field), then moved to 2m + 2 + par.
+            // both with packed 16-bit ops against their thresholds t (thi4 for c = 4 and 0 above
+            // in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per half:
+            // t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept bits
+            // are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved to
+            // 2m + 2 + par.
             const u16x2 t4 = {(uint16_t)thi4, (uint16_t)thi4};
             const u16x2 one = {1, 1};
             u16x2 zmin = {0xFFFF, 0xFFFF};
             uint32_t raw = 0;
+            // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
+            // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par
+            const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
+            const uint32_t* TT = jtab + F::JDWORDS;  // the pair-threshold table
 #pragma unroll
             for (int m = 0; m < H; m += 2) {
                 const int hm = PH + y * H + m;
@@ -171,9 +189,15 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
                 if (MODE == 2) {
                     zmin = __builtin_elementwise_min(zmin, w);
                 } else {
-                    const u16x2 a = __builtin_elementwise_min(__builtin_elementwise_sub_sat(t4, w), one);
-                    raw |= __builtin_bit_cast(uint32_t, a) << (2 * m + par);
-                    zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t4, w));
+                    const u16x2 t = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
+                    const u16x2 d = __builtin_elementwise_sub_sat(t, w);
+                    // min(d, 1) per half, written out: as an expression the optimiser turns it
+                    // into d != 0, i.e. two compares, two selects and a byte permute per pair
+                    uint32_t a;
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(a) : "v"(d), "v"(one));
+                    raw |= a << (2 * m + par);
+                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t, w));
+                    else zmin = __builtin_elementwise_min(zmin, w - t);
                 }
             }
             tie = zmin.x == 0 || zmin.y == 0;
@@ -346,10 +370,10 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
     using F = FastLayout<L, LPR>;
     if (st->status) return;  // sticky error: the population stays as it is
     extern __shared__ uint32_t lds[];
-    build_jtab<L, LPR>(st, lds, threadIdx.x, blockDim.x);
+    build_jtab<L, LPR>(st, lds, th, threadIdx.x, blockDim.x);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::JDWORDS) + wave * (F::ROW_BYTES / 2);
+    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::TAB_DWORDS) + wave * (F::ROW_BYTES / 2);
     const int64_t rbase = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * F::RPW;
     if (rbase >= st->R) return;
     sweep_tile<L, LAYOUT, LPR, MODE>(st, rbase, lds, rows, lane, p, th);
@@ -394,9 +418,9 @@ __device__ __forceinline__ void batch_tile(const pa_state* st, int64_t local, ui
 {
     constexpr int LPR = batch_lpr(L);
     using F = FastLayout<L, LPR>;
-    build_jtab<L, LPR>(st, lds, lane, 64);
+    build_jtab<L, LPR>(st, lds, th, lane, 64);
     wave_sync();
-    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::JDWORDS);
+    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::TAB_DWORDS);
     sweep_tile<L, LAYOUT, LPR, MODE>(st, local * F::RPW, lds, rows, lane, p, th);
 }
 

@@ -209,6 +209,12 @@ def test_threshold_values():
     assert o.threshold(0.0, 12)[1]
     # e^{-40} 2^64 = 78.4...: a 64-bit threshold keeps acceptances a 32-bit one rounds away
     assert o.threshold(5.0, 8)[0] == 78
+    # near beta = 0 the probabilities sit next to 1: e^{-4e-17} is within half an ulp of 1, so it
+    # is 1 (always accept); e^{-8e-17} and e^{-1.2e-16} round to 1 - 2^-53, whose threshold is
+    # (1 - 2^-53) 2^64 = 2^64 - 2^11 (first 16 bits 0xFFFF)
+    assert o.threshold(1e-17, 4) == (0, True)
+    assert o.threshold(1e-17, 8) == (2 ** 64 - 2 ** 11, False)
+    assert o.threshold(1e-17, 12) == (2 ** 64 - 2 ** 11, False)
 
 
 def _half_sweep_matrix(dim, L, J, beta, colour, states, index):

@@ -76,7 +76,9 @@ def test_init_with_host_couplings():
     assert np.array_equal(s, so) and np.array_equal(E, Eo)
 
 
-SWEEP_BETAS = [0.0, 0.35, 1.2, 2.0, 5.0]  # regimes: 0 (beta < 1.39), 1 (1.39 .. 2.77), 2
+# regimes: 0 (beta < 1.39), 1 (1.39 .. 2.77), 2.  At beta = 1e-17 exp(-4 beta) rounds to 1 (class
+# c = 4 always accepts) while c = 5, 6 have T64 = 2^64 - 2^11: first-look threshold 0xFFFF
+SWEEP_BETAS = [0.0, 1e-17, 0.35, 1.2, 2.0, 5.0]
 
 
 @pytest.mark.parametrize("dim,L,layout,R0", INIT_CASES)
