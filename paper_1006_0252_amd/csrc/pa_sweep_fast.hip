@@ -60,12 +60,15 @@ template <int L, int LPR>
 struct FastLayout {
     static constexpr int NR = L * L;
     static constexpr int H = L / 2;
+    // L = 0 mod 4: rows y and y + L/2 of a plane share one 32-bit word (low and high half)
+    static constexpr bool PAIRED = L % 4 == 0;
+    static constexpr int JROWS = PAIRED ? L / 2 : L;            // coupling-mask entries per plane
     static constexpr int RPW = 64 / LPR;
     static constexpr int PL = L / LPR;                          // planes per lane
     static constexpr int PADW = LPR == 4 ? 8 : 0;               // u16 padding per plane (bank stagger)
     static constexpr int PSTRIDE = L * RPW + PADW;              // u16 per plane
     static constexpr int JPAD = LPR == 4 ? 4 : 0;
-    static constexpr int JSTRIDE = L * 8 + JPAD;                // dwords of coupling masks per plane
+    static constexpr int JSTRIDE = JROWS * 8 + JPAD;            // dwords of coupling masks per plane
     static constexpr int JDWORDS = L * JSTRIDE;
     static constexpr int TDWORDS = 16;                          // pair-threshold table after the masks
     static constexpr int TAB_DWORDS = JDWORDS + TDWORDS;        // block-shared tables
@@ -77,8 +80,27 @@ struct FastLayout {
 // that the Philox phase of a plane is uniform over the wave)
 __host__ __device__ constexpr int batch_lpr(int L) { return L % 4 != 0 ? 1 : (L >= 12 ? 4 : (L >= 8 ? 2 : 1)); }
 
-// coupling masks per row, entries +x, +y, +z, -x, -y, -z bonds with J = -1; then the
-// thresholds of two consecutive sites of a colour by their class bits: entry
+// coupling masks of row rho = y + L z, entries +x, +y, +z, -x, -y, -z bonds with J = -1 (bit x)
+template <int L>
+__device__ void row_masks(const int8_t* J, int rho, uint32_t m[6])
+{
+    const int y = rho % L, z = rho / L;
+    const int ym = (y + L - 1) % L, zm = (z + L - 1) % L;
+    for (int k = 0; k < 6; ++k) m[k] = 0;
+    for (int x = 0; x < L; ++x) {
+        const int i = x + L * rho;
+        const int xm = (x + L - 1) % L;
+        m[0] |= (uint32_t)(J[3 * i + 0] < 0) << x;
+        m[1] |= (uint32_t)(J[3 * i + 1] < 0) << x;
+        m[2] |= (uint32_t)(J[3 * i + 2] < 0) << x;
+        m[3] |= (uint32_t)(J[3 * (xm + L * rho) + 0] < 0) << x;
+        m[4] |= (uint32_t)(J[3 * (x + L * (ym + L * z)) + 1] < 0) << x;
+        m[5] |= (uint32_t)(J[3 * (x + L * (y + L * zm)) + 2] < 0) << x;
+    }
+}
+
+// the block-shared tables: coupling masks per row (rows y and y + L/2 in one entry when paired);
+// then the thresholds of two consecutive sites of a colour by their class bits: entry
 // a + 4 b (a, b = c0 + 2 c1 of the first and second site) holds thi(a) | thi(b) << 16, with
 // class index 0, 1, 2 for c = 4, 5, 6 (3 cannot occur at a candidate site).  A threshold of
 // 0x10000 (always accept) is stored as 0xFFFF: every u below it accepts, and u = 0xFFFF equals
@@ -93,22 +115,13 @@ __device__ void build_jtab(const pa_state* st, uint32_t* jtab, const FastThr& th
         jtab[F::JDWORDS + tid] = t[tid & 3] | (t[tid >> 2] << 16);
     }
     const int8_t* J = st->J;
-    for (int rho = tid; rho < F::NR; rho += nthr) {
-        const int y = rho % L, z = rho / L;
-        const int ym = (y + L - 1) % L, zm = (z + L - 1) % L;
-        uint32_t m[6] = {0, 0, 0, 0, 0, 0};
-        for (int x = 0; x < L; ++x) {
-            const int i = x + L * rho;
-            const int xm = (x + L - 1) % L;
-            m[0] |= (uint32_t)(J[3 * i + 0] < 0) << x;
-            m[1] |= (uint32_t)(J[3 * i + 1] < 0) << x;
-            m[2] |= (uint32_t)(J[3 * i + 2] < 0) << x;
-            m[3] |= (uint32_t)(J[3 * (xm + L * rho) + 0] < 0) << x;
-            m[4] |= (uint32_t)(J[3 * (x + L * (ym + L * z)) + 1] < 0) << x;
-            m[5] |= (uint32_t)(J[3 * (x + L * (y + L * zm)) + 2] < 0) << x;
-        }
+    for (int e_i = tid; e_i < L * F::JROWS; e_i += nthr) {
+        const int z = e_i / F::JROWS, y = e_i % F::JROWS;
+        uint32_t m[6], mh[6] = {0, 0, 0, 0, 0, 0};
+        row_masks<L>(J, y + L * z, m);
+        if (F::PAIRED) row_masks<L>(J, y + L / 2 + L * z, mh);
         uint32_t* e = jtab + z * F::JSTRIDE + y * 8;
-        for (int k = 0; k < 6; ++k) e[k] = m[k];
+        for (int k = 0; k < 6; ++k) e[k] = m[k] | (mh[k] << 16);
         e[6] = 0;
         e[7] = 0;
     }
@@ -121,7 +134,20 @@ struct PlaneCtx {
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-// one colour of one plane z of this lane's replica
+// bit-sliced count of the six bond words: c = c0 + 2 c1 + 4 c2 bonds with J s_i s_j = -1 per bit
+__device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4,
+                                           uint32_t b5, uint32_t& c0, uint32_t& c1, uint32_t& c2)
+{
+    const uint32_t s1 = b0 ^ b1 ^ b2, k1c = (b0 & b1) | (b2 & (b0 ^ b1));
+    const uint32_t s2 = b3 ^ b4 ^ b5, k2c = (b3 & b4) | (b5 & (b3 ^ b4));
+    c0 = s1 ^ s2;
+    const uint32_t k3c = s1 & s2;
+    c1 = k1c ^ k2c ^ k3c;
+    c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
+}
+
+// one colour of one plane z of this lane's replica, L = 2 mod 4 (one row per word; the half-
+// sites of a colour per row are odd in number, so each site takes its own 16-bit field)
 template <int L, int LPR, int MODE, int PH>
 __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jtab, int z, int q, int col,
                                              const PlaneCtx& c, const FastThr& th)
@@ -150,59 +176,13 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
         const uint32_t zmv = Pm[y * RPW];
         const uint32_t* jr = JT + y * 8;
         const uint32_t dup = own | (own << L);
-        const uint32_t b0 = own ^ (dup >> 1) ^ jr[0];
-        const uint32_t b1 = own ^ yp ^ jr[1];
-        const uint32_t b2 = own ^ zpv ^ jr[2];
-        const uint32_t b3 = own ^ (dup >> (L - 1)) ^ jr[3];
-        const uint32_t b4 = own ^ ym ^ jr[4];
-        const uint32_t b5 = own ^ zmv ^ jr[5];
-        const uint32_t s1 = b0 ^ b1 ^ b2, k1c = (b0 & b1) | (b2 & (b0 ^ b1));
-        const uint32_t s2 = b3 ^ b4 ^ b5, k2c = (b3 & b4) | (b5 & (b3 ^ b4));
-        const uint32_t c0 = s1 ^ s2, k3c = s1 & s2;
-        const uint32_t c1 = k1c ^ k2c ^ k3c;
-        const uint32_t c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
+        uint32_t c0, c1, c2;
+        bond_count(own ^ (dup >> 1) ^ jr[0], own ^ yp ^ jr[1], own ^ zpv ^ jr[2], own ^ (dup >> (L - 1)) ^ jr[3],
+                   own ^ ym ^ jr[4], own ^ zmv ^ jr[5], c0, c1, c2);
         const uint32_t colmask = (y & 1) ? cmB : cmA;
         const int par = p0 ^ (y & 1);
         uint32_t acc = 0;
         bool tie = false;
-        if constexpr (H % 2 == 0) {
-            // sites m and m + 1 (m even) take the two 16-bit fields of one Philox word: compare
-            // both with packed 16-bit ops against their thresholds t (thi4 for c = 4 and 0 above
-            // in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per half:
-            // t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept bits
-            // are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved to
-            // 2m + 2 + par.
-            const u16x2 t4 = {(uint16_t)thi4, (uint16_t)thi4};
-            const u16x2 one = {1, 1};
-            u16x2 zmin = {0xFFFF, 0xFFFF};
-            uint32_t raw = 0;
-            // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
-            // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par
-            const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
-            const uint32_t* TT = jtab + F::JDWORDS;  // the pair-threshold table
-#pragma unroll
-            for (int m = 0; m < H; m += 2) {
-                const int hm = PH + y * H + m;
-                if (hm % 8 == 0 || (y == 0 && m == 0))
-                    rnd = philox10(cb + (uint32_t)(hm / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-                const u16x2 w = __builtin_bit_cast(u16x2, word_of(rnd, (hm & 7) >> 1));
-                if (MODE == 2) {
-                    zmin = __builtin_elementwise_min(zmin, w);
-                } else {
-                    const u16x2 t = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
-                    const u16x2 d = __builtin_elementwise_sub_sat(t, w);
-                    // min(d, 1) per half, written out: as an expression the optimiser turns it
-                    // into d != 0, i.e. two compares, two selects and a byte permute per pair
-                    uint32_t a;
-                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(a) : "v"(d), "v"(one));
-                    raw |= a << (2 * m + par);
-                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t, w));
-                    else zmin = __builtin_elementwise_min(zmin, w - t);
-                }
-            }
-            tie = zmin.x == 0 || zmin.y == 0;
-            acc = (raw & 0xFFFFu) | (raw >> 14);
-        } else {
 #pragma unroll
         for (int m = 0; m < H; ++m) {
             const int hm = PH + y * H + m;  // position counted from the start of call cb
@@ -225,7 +205,6 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
                 tie |= (u == thi);
             }
         }
-        }
         uint32_t flip;
         if (MODE == 2) flip = colmask & ~c2;
         else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
@@ -241,6 +220,117 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
     }
 }
 
+// one colour of one plane z of this lane's replica, L = 0 mod 4: rows y and y + L/2 (same colour
+// pattern, not neighbours) sit in the low and high half of one 32-bit word, so one bit-sliced
+// count serves both.  The y + 1 word of the last pair and the y - 1 word of the first are the
+// first and last pair with halves swapped.
+template <int L, int LPR, int MODE>
+__device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint32_t* jtab, int z, int q, int col,
+                                                   const PlaneCtx& c, const FastThr& th)
+{
+    using F = FastLayout<L, LPR>;
+    constexpr int H = F::H, Y = L / 2, RPW = F::RPW, PS = F::PSTRIDE / 2;
+    constexpr uint32_t MASK = (1u << L) - 1u;
+    constexpr uint32_t MASKP = MASK | (MASK << 16);
+    constexpr uint32_t XP = (MASK >> 1) | ((MASK >> 1) << 16);  // x <= L - 2 in each half: x + 1 from w >> 1
+    constexpr uint32_t XM = XP << 1;                             // x >= 1: x - 1 from w << 1
+    const int zp = (z + 1 == L) ? 0 : z + 1;
+    const int zm = (z == 0) ? L - 1 : z - 1;
+    uint32_t* P0 = rows32 + z * PS + q;
+    const uint32_t* Pp = rows32 + zp * PS + q;
+    const uint32_t* Pm = rows32 + zm * PS + q;
+    const uint32_t* JT = jtab + z * F::JSTRIDE;
+    const uint32_t* TT = jtab + F::JDWORDS;               // the pair-threshold table
+    const uint32_t cb = (uint32_t)((z * (L * H)) >> 3);  // Philox call of the plane's first half-site
+    const int p0 = (col + z) & 1;                        // x parity of colour col at even y
+    const uint32_t cmA = (p0 ? 0xAAAAAAAAu : 0x55555555u) & MASKP;
+    const uint32_t cmB = (p0 ? 0x55555555u : 0xAAAAAAAAu) & MASKP;
+    const u16x2 t4 = {(uint16_t)th.thi4, (uint16_t)th.thi4};
+    const u16x2 one = {1, 1};
+    uint4v rndA = {0, 0, 0, 0}, rndB = {0, 0, 0, 0};
+#pragma unroll
+    for (int yy = 0; yy < Y; ++yy) {
+        const uint32_t own = P0[yy * RPW];
+        uint32_t yp = P0[((yy + 1) % Y) * RPW];
+        uint32_t ym = P0[((yy + Y - 1) % Y) * RPW];
+        if (yy == Y - 1) yp = (yp >> 16) | (yp << 16);
+        if (yy == 0) ym = (ym >> 16) | (ym << 16);
+        const uint32_t zpv = Pp[yy * RPW];
+        const uint32_t zmv = Pm[yy * RPW];
+        const uint32_t* jr = JT + yy * 8;
+        // x + 1 and x - 1 neighbours, periodic within each half
+        const uint32_t rp = ((own >> 1) & XP) | ((own << (L - 1)) & ~XP);
+        const uint32_t rm = ((own << 1) & XM) | ((own >> (L - 1)) & ~XM);
+        uint32_t c0, c1, c2;
+        bond_count(own ^ rp ^ jr[0], own ^ yp ^ jr[1], own ^ zpv ^ jr[2], own ^ rm ^ jr[3], own ^ ym ^ jr[4],
+                   own ^ zmv ^ jr[5], c0, c1, c2);
+        const uint32_t colmask = (yy & 1) ? cmB : cmA;
+        const int par = p0 ^ (yy & 1);
+        // sites m and m + 1 (m even) of a row take the two 16-bit fields of one Philox word:
+        // both are compared with packed 16-bit ops against their thresholds t (thi4 for c = 4
+        // and 0 above in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per
+        // half: t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept
+        // bits are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved
+        // to 2m + 2 + par.
+        u16x2 zmin = {0xFFFF, 0xFFFF};
+        uint32_t rawA = 0, rawB = 0;
+        // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
+        // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par (+ 16).  With
+        // L = 16 the c1 bit of the high row's x = 15 would leave the word: that row takes c1(x)
+        // at bit x and c0(x) at bit x - 1 instead (the same nibble, one bit lower)
+        const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
+        const uint32_t c01h = L == 16 ? ((c1 & colmask) | ((c0 >> 1) & ~colmask)) : c01;
+        constexpr int OFFH = L == 16 ? 15 : 16;
+#pragma unroll
+        for (int m = 0; m < H; m += 2) {
+            const int hA = yy * H + m, hB = (yy + Y) * H + m;  // half-site positions from call cb
+            if (hA % 8 == 0 || (yy == 0 && m == 0))
+                rndA = philox10(cb + (uint32_t)(hA / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+            if (hB % 8 == 0 || (yy == 0 && m == 0))
+                rndB = philox10(cb + (uint32_t)(hB / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+            const u16x2 wA = __builtin_bit_cast(u16x2, word_of(rndA, (hA & 7) >> 1));
+            const u16x2 wB = __builtin_bit_cast(u16x2, word_of(rndB, (hB & 7) >> 1));
+            if (MODE == 2) {
+                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
+            } else {
+                const u16x2 tA = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
+                const u16x2 tB = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01h >> (OFFH + 2 * m + par)) & 15u]);
+                const u16x2 dA = __builtin_elementwise_sub_sat(tA, wA);
+                const u16x2 dB = __builtin_elementwise_sub_sat(tB, wB);
+                // min(d, 1) per half, written out: as an expression the optimiser turns it into
+                // d != 0, i.e. two compares, two selects and a byte permute per word
+                uint32_t aA, aB;
+                asm("v_pk_min_u16 %0, %1, %2" : "=v"(aA) : "v"(dA), "v"(one));
+                asm("v_pk_min_u16 %0, %1, %2" : "=v"(aB) : "v"(dB), "v"(one));
+                rawA |= aA << (2 * m + par);
+                rawB |= aB << (2 * m + par);
+                if (MODE == 1)
+                    zmin = __builtin_elementwise_min(
+                        zmin, __builtin_elementwise_min(__builtin_elementwise_min(wA - tA, wA),
+                                                        __builtin_elementwise_min(wB - tB, wB)));
+                else
+                    zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA - tA, wB - tB));
+            }
+        }
+        const bool tie = zmin.x == 0 || zmin.y == 0;
+        const uint32_t acc = (rawA & 0xFFFFu) | (rawA >> 14) | (((rawB & 0xFFFFu) | (rawB >> 14)) << 16);
+        uint32_t flip;
+        if (MODE == 2) flip = colmask & ~c2;
+        else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+        else flip = colmask & (~c2 | acc);
+        if (tie) {
+            const uint32_t cand = c2 & colmask;
+            const int rA = yy + L * z, rB = yy + Y + L * z;
+            const uint32_t accA = resolve_row(c0, c1, cand & MASK, par, rA * H, H, L * rA, c.rr, c.ctr2, c.k0, c.k1, th);
+            const uint32_t accB = resolve_row(c0 >> 16, c1 >> 16, (cand >> 16) & MASK, par, rB * H, H, L * rB, c.rr,
+                                              c.ctr2, c.k0, c.k1, th);
+            flip = colmask & (~c2 | accA | (accB << 16));
+        }
+        if (!c.valid) flip = 0;
+        P0[yy * RPW] = own ^ flip;
+    }
+}
+
 // N_S sweeps of the RPW replicas rbase .. rbase + RPW - 1 of one run (one wave)
 template <int L, int LAYOUT, int LPR, int MODE>
 __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, const uint32_t* jtab, uint16_t* rows, int lane,
@@ -253,6 +343,9 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     static_assert(L % 2 == 0 && L <= 16 && L % LPR == 0, "fast sweep geometry");
     static_assert(L % 4 == 0 || LPR == 1, "L = 2 mod 4 needs one lane per replica");
     const int q = lane % RPW, j = lane / RPW;
+    // u16 slot of row y from the lane's plane base: rows y and y + L/2 are the halves of word
+    // y mod L/2 when paired
+    auto row_slot = [](int y) { return F::PAIRED ? 2 * (y % (L / 2)) * RPW + y / (L / 2) : y * RPW; };
     const int64_t R = st->R;
     const int cur = st->cur;
     const int64_t r = rbase + q;
@@ -268,7 +361,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll 1
     for (int t = 0; t < PL; ++t) {
         const int z = j * PL + t;
-        uint16_t* P = rows + z * PSTRIDE + q;
+        uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
         for (int y = 0; y < L; ++y) {
             const int rho = y + L * z;
             uint32_t v = 0;
@@ -284,7 +377,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll
                 for (int x = 0; x < L; ++x) v |= (uint32_t)(a[x] & 1) << x;
             }
-            P[y * RPW] = (uint16_t)v;
+            P[row_slot(y)] = (uint16_t)v;
         }
     }
     wave_sync();
@@ -295,8 +388,8 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
             c.ctr2 = (uint32_t)(2 * t_sweep + col);
             for (int t = 0; t < PL; ++t) {
                 const int z = j * PL + t;
-                if constexpr (L % 4 == 0) {
-                    plane_update<L, LPR, MODE, 0>(rows, jtab, z, q, col, c, th);
+                if constexpr (F::PAIRED) {
+                    plane_update_pairs<L, LPR, MODE>(reinterpret_cast<uint32_t*>(rows), jtab, z, q, col, c, th);
                 } else {
                     switch ((z * (L * H)) & 7) {
                         case 0: plane_update<L, LPR, MODE, 0>(rows, jtab, z, q, col, c, th); break;
@@ -316,17 +409,36 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     for (int t = 0; t < PL; ++t) {
         const int z = j * PL + t;
         const int zp = (z + 1 == L) ? 0 : z + 1;
-        const uint16_t* P0 = rows + z * PSTRIDE + q;
-        const uint16_t* Pp = rows + zp * PSTRIDE + q;
         const uint32_t* JT = jtab + z * F::JSTRIDE;
+        if constexpr (F::PAIRED) {
+            constexpr int Y = L / 2, PS = PSTRIDE / 2;
+            constexpr uint32_t MASKP = MASK | (MASK << 16);
+            constexpr uint32_t XP = (MASK >> 1) | ((MASK >> 1) << 16);
+            const uint32_t* P0 = reinterpret_cast<const uint32_t*>(rows) + z * PS + q;
+            const uint32_t* Pp = reinterpret_cast<const uint32_t*>(rows) + zp * PS + q;
 #pragma unroll
-        for (int y = 0; y < L; ++y) {
-            const uint32_t own = P0[y * RPW];
-            const uint32_t dup = own | (own << L);
-            const uint32_t* jr = JT + y * 8;
-            neg += __popc((own ^ (dup >> 1) ^ jr[0]) & MASK);
-            neg += __popc((own ^ P0[((y + 1) % L) * RPW] ^ jr[1]) & MASK);
-            neg += __popc((own ^ Pp[y * RPW] ^ jr[2]) & MASK);
+            for (int yy = 0; yy < Y; ++yy) {
+                const uint32_t own = P0[yy * RPW];
+                uint32_t yp = P0[((yy + 1) % Y) * RPW];
+                if (yy == Y - 1) yp = (yp >> 16) | (yp << 16);
+                const uint32_t rp = ((own >> 1) & XP) | ((own << (L - 1)) & ~XP);
+                const uint32_t* jr = JT + yy * 8;
+                neg += __popc((own ^ rp ^ jr[0]) & MASKP);
+                neg += __popc((own ^ yp ^ jr[1]) & MASKP);
+                neg += __popc((own ^ Pp[yy * RPW] ^ jr[2]) & MASKP);
+            }
+        } else {
+            const uint16_t* P0 = rows + z * PSTRIDE + q;
+            const uint16_t* Pp = rows + zp * PSTRIDE + q;
+#pragma unroll
+            for (int y = 0; y < L; ++y) {
+                const uint32_t own = P0[y * RPW];
+                const uint32_t dup = own | (own << L);
+                const uint32_t* jr = JT + y * 8;
+                neg += __popc((own ^ (dup >> 1) ^ jr[0]) & MASK);
+                neg += __popc((own ^ P0[((y + 1) % L) * RPW] ^ jr[1]) & MASK);
+                neg += __popc((own ^ Pp[y * RPW] ^ jr[2]) & MASK);
+            }
         }
     }
     for (int off = RPW; off < 64; off <<= 1) neg += __shfl_xor(neg, off, 64);
@@ -339,10 +451,10 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll 1
         for (int t = 0; t < PL; ++t) {
             const int z = j * PL + t;
-            const uint16_t* P = rows + z * PSTRIDE + q;
+            const uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
             for (int y = 0; y < L; ++y) {
                 const int rho = y + L * z;
-                const uint32_t v = P[y * RPW];
+                const uint32_t v = P[row_slot(y)];
                 if (LAYOUT == PA_BITS64) {
                     uint8_t* a = (uint8_t*)st->spins[cur] + (((rw >> 6) * NR + rho) * 64 + (rw & 63)) * WB;
                     if (WB == 1) *a = (uint8_t)v;
