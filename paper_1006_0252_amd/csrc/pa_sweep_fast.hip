@@ -33,25 +33,31 @@ struct FastThr {
     uint64_t T4, T5, T6;
 };
 
-// exact random-acceptance mask of the candidate sites (c >= 4) of one row
-static __device__ __noinline__ uint32_t resolve_row(uint32_t c0, uint32_t c1, uint32_t cand, int par, int hbase,
-                                                    int H, int ibase, uint32_t rr, uint32_t ctr2, uint32_t k0,
-                                                    uint32_t k1, FastThr th)
+// exact random-acceptance mask of the candidate sites (c >= 4) of nh rows held in the 16-bit
+// halves of the words c0, c1, cand (nh = 2: the second row's half-sites start hstep and its sites
+// istep further on).  The thresholds come as scalars: a structure passed by value to this
+// out-of-line call would go through private (scratch) memory.
+static __device__ __noinline__ uint32_t resolve_rows(uint32_t c0, uint32_t c1, uint32_t cand, int par, int nh, int H,
+                                                     int hbase, int hstep, int ibase, int istep, uint32_t rr,
+                                                     uint32_t ctr2, uint32_t k0, uint32_t k1, uint32_t thi4,
+                                                     uint32_t thi5, uint32_t thi6, uint64_t T4, uint64_t T5, uint64_t T6)
 {
     uint32_t racc = 0;
-    for (int m = 0; m < H; ++m) {
-        const int x = 2 * m + par;
-        if (!((cand >> x) & 1u)) continue;
-        const int h = hbase + m;
-        const uint4v v = philox10((uint32_t)(h >> 3), rr, ctr2, kTagMet, k0, k1);
-        const uint32_t u = field16(v, h & 7);
-        const int cls = 4 + (int)((c0 >> x) & 1u) + 2 * (int)((c1 >> x) & 1u);
-        const uint32_t thi = cls == 4 ? th.thi4 : (cls == 5 ? th.thi5 : th.thi6);
-        const uint64_t T = cls == 4 ? th.T4 : (cls == 5 ? th.T5 : th.T6);
-        bool a;
-        if (u != thi) a = u < thi;
-        else a = tie_accept(u, T, (uint32_t)(ibase + x), rr, ctr2, k0, k1);
-        racc |= (uint32_t)a << x;
+    for (int hh = 0; hh < nh; ++hh) {
+        for (int m = 0; m < H; ++m) {
+            const int x = 2 * m + par, b = 16 * hh + x;
+            if (!((cand >> b) & 1u)) continue;
+            const int h = hbase + hh * hstep + m;
+            const uint4v v = philox10((uint32_t)(h >> 3), rr, ctr2, kTagMet, k0, k1);
+            const uint32_t u = field16(v, h & 7);
+            const int cls = 4 + (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
+            const uint32_t thi = cls == 4 ? thi4 : (cls == 5 ? thi5 : thi6);
+            const uint64_t T = cls == 4 ? T4 : (cls == 5 ? T5 : T6);
+            bool a;
+            if (u != thi) a = u < thi;
+            else a = tie_accept(u, T, (uint32_t)(ibase + hh * istep + x), rr, ctr2, k0, k1);
+            racc |= (uint32_t)a << b;
+        }
     }
     return racc;
 }
@@ -212,7 +218,8 @@ __device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jta
         if (tie) {
             const uint32_t cand = c2 & colmask;
             const int rho = y + L * z;
-            const uint32_t racc = resolve_row(c0, c1, cand, par, rho * H, H, L * rho, c.rr, c.ctr2, c.k0, c.k1, th);
+            const uint32_t racc = resolve_rows(c0, c1, cand, par, 1, H, rho * H, 0, L * rho, 0, c.rr, c.ctr2, c.k0,
+                                               c.k1, th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
             flip = colmask & (~c2 | racc);
         }
         if (!c.valid) flip = 0;
@@ -320,11 +327,10 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
         else flip = colmask & (~c2 | acc);
         if (tie) {
             const uint32_t cand = c2 & colmask;
-            const int rA = yy + L * z, rB = yy + Y + L * z;
-            const uint32_t accA = resolve_row(c0, c1, cand & MASK, par, rA * H, H, L * rA, c.rr, c.ctr2, c.k0, c.k1, th);
-            const uint32_t accB = resolve_row(c0 >> 16, c1 >> 16, (cand >> 16) & MASK, par, rB * H, H, L * rB, c.rr,
-                                              c.ctr2, c.k0, c.k1, th);
-            flip = colmask & (~c2 | accA | (accB << 16));
+            const int rA = yy + L * z;  // the high row is rA + L/2
+            const uint32_t racc = resolve_rows(c0, c1, cand, par, 2, H, rA * H, Y * H, L * rA, L * Y, c.rr, c.ctr2,
+                                               c.k0, c.k1, th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
+            flip = colmask & (~c2 | racc);
         }
         if (!c.valid) flip = 0;
         P0[yy * RPW] = own ^ flip;
@@ -332,7 +338,60 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
 }
 
 // N_S sweeps of the RPW replicas rbase .. rbase + RPW - 1 of one run (one wave)
-template <int L, int LAYOUT, int LPR, int MODE>
+// u16 slot of row y of a plane, from the lane's plane base: rows y and y + L/2 are the halves of
+// word y mod L/2 when paired
+template <int L, int LPR>
+__device__ __forceinline__ int row_slot(int y)
+{
+    using F = FastLayout<L, LPR>;
+    return F::PAIRED ? 2 * (y % (L / 2)) * F::RPW + y / (L / 2) : y * F::RPW;
+}
+
+// The rows of the 64 replicas of bit-packed group g (two bytes per row and replica) between HBM
+// and the LDS rows of a block whose waves hold the group's replicas in order (replica r of the
+// group: wave r / RPW, slot r % RPW).  Each thread moves 4 replicas of a row as one 8-byte word,
+// so a row is one 128-byte line; a wave's own share of a line is only 32 bytes.  Stores skip the
+// replicas at or past R.
+template <int L, int LPR, bool STORE>
+__device__ void group_rows_io(const pa_state* st, int64_t g, uint16_t* rows0, int64_t R, int tid, int nthr)
+{
+    using F = FastLayout<L, LPR>;
+    constexpr int RPW = F::RPW, NR = F::NR;
+    static_assert(L > 8, "two bytes per row word");
+    uint64_t* G = reinterpret_cast<uint64_t*>((uint8_t*)st->spins[st->cur] + g * (int64_t)NR * 128);
+    for (int e = tid; e < NR * 16; e += nthr) {
+        const int rho = e >> 4, k = e & 15;  // replicas 4k .. 4k + 3 of row rho
+        const int z = rho / L, y = rho % L;
+        uint16_t* P = rows0 + z * F::PSTRIDE + row_slot<L, LPR>(y);
+        uint16_t* slot[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * k + i, w = r / RPW, qq = r % RPW;
+            slot[i] = P + w * (F::ROW_BYTES / 2) + (F::PAIRED ? 2 * qq : qq);
+        }
+        if (!STORE) {
+            const uint64_t v = G[e];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) *slot[i] = (uint16_t)(v >> (16 * i));
+        } else {
+            const int64_t r0 = g * 64 + 4 * k;
+            if (r0 + 3 < R) {
+                uint64_t v = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v |= (uint64_t)*slot[i] << (16 * i);
+                G[e] = v;
+            } else {
+                uint16_t* G16 = reinterpret_cast<uint16_t*>(G + e);
+                for (int i = 0; i < 4; ++i)
+                    if (r0 + i < R) G16[i] = *slot[i];
+            }
+        }
+    }
+}
+
+// N_S sweeps of the tile; IO: the tile's rows are loaded and stored here (else the block moves
+// whole groups with group_rows_io around the call)
+template <int L, int LAYOUT, int LPR, int MODE, bool IO = true>
 __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, const uint32_t* jtab, uint16_t* rows, int lane,
                            const SweepParams& p, const FastThr& th)
 {
@@ -343,9 +402,6 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     static_assert(L % 2 == 0 && L <= 16 && L % LPR == 0, "fast sweep geometry");
     static_assert(L % 4 == 0 || LPR == 1, "L = 2 mod 4 needs one lane per replica");
     const int q = lane % RPW, j = lane / RPW;
-    // u16 slot of row y from the lane's plane base: rows y and y + L/2 are the halves of word
-    // y mod L/2 when paired
-    auto row_slot = [](int y) { return F::PAIRED ? 2 * (y % (L / 2)) * RPW + y / (L / 2) : y * RPW; };
     const int64_t R = st->R;
     const int cur = st->cur;
     const int64_t r = rbase + q;
@@ -359,7 +415,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     // stay rolled: unrolled, their 64-bit row addresses are shared between the two and held live
     // across the sweeps, which costs two thirds of the waves per SIMD)
 #pragma unroll 1
-    for (int t = 0; t < PL; ++t) {
+    for (int t = 0; t < (IO ? PL : 0); ++t) {
         const int z = j * PL + t;
         uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
         for (int y = 0; y < L; ++y) {
@@ -377,7 +433,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll
                 for (int x = 0; x < L; ++x) v |= (uint32_t)(a[x] & 1) << x;
             }
-            P[row_slot(y)] = (uint16_t)v;
+            P[row_slot<L, LPR>(y)] = (uint16_t)v;
         }
     }
     wave_sync();
@@ -449,12 +505,12 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
     asm volatile("" : "+v"(rw));
     if (c.valid) {
 #pragma unroll 1
-        for (int t = 0; t < PL; ++t) {
+        for (int t = 0; t < (IO ? PL : 0); ++t) {
             const int z = j * PL + t;
             const uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
             for (int y = 0; y < L; ++y) {
                 const int rho = y + L * z;
-                const uint32_t v = P[row_slot(y)];
+                const uint32_t v = P[row_slot<L, LPR>(y)];
                 if (LAYOUT == PA_BITS64) {
                     uint8_t* a = (uint8_t*)st->spins[cur] + (((rw >> 6) * NR + rho) * 64 + (rw & 63)) * WB;
                     if (WB == 1) *a = (uint8_t)v;
@@ -485,8 +541,23 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
     build_jtab<L, LPR>(st, lds, th, threadIdx.x, blockDim.x);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* rows = reinterpret_cast<uint16_t*>(lds + F::TAB_DWORDS) + wave * (F::ROW_BYTES / 2);
+    uint16_t* rows0 = reinterpret_cast<uint16_t*>(lds + F::TAB_DWORDS);
+    uint16_t* rows = rows0 + wave * (F::ROW_BYTES / 2);
     const int64_t rbase = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * F::RPW;
+    if constexpr (LAYOUT == PA_BITS64 && L > 8) {
+        // the block's waves hold one whole 64-replica group: it moves between HBM and LDS in
+        // whole lines, block-wide (every wave reaches both barriers)
+        if ((int)(blockDim.x >> 6) * F::RPW == 64) {
+            const int64_t R = st->R;
+            if ((int64_t)blockIdx.x * 64 >= R) return;  // the whole block is past the population
+            group_rows_io<L, LPR, false>(st, blockIdx.x, rows0, R, threadIdx.x, blockDim.x);
+            __syncthreads();
+            if (rbase < R) sweep_tile<L, LAYOUT, LPR, MODE, false>(st, rbase, lds, rows, lane, p, th);
+            __syncthreads();
+            group_rows_io<L, LPR, true>(st, blockIdx.x, rows0, R, threadIdx.x, blockDim.x);
+            return;
+        }
+    }
     if (rbase >= st->R) return;
     sweep_tile<L, LAYOUT, LPR, MODE>(st, rbase, lds, rows, lane, p, th);
 }
