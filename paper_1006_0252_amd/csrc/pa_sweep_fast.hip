@@ -62,6 +62,38 @@ static __device__ __noinline__ uint32_t resolve_rows(uint32_t c0, uint32_t c1, u
     return racc;
 }
 
+// The same decision for the two rows of a word when each row's eight half-sites of a colour are
+// exactly one Philox call (L = 16): the first looks come from the rows' words a, b, already drawn
+// on the hot path, and only a first-look tie draws the 48 low bits.
+static __device__ __noinline__ uint32_t resolve_pair_words(uint32_t c0, uint32_t c1, uint32_t cand, int par, int ibase,
+                                                           int istep, uint32_t a0, uint32_t a1, uint32_t a2,
+                                                           uint32_t a3, uint32_t b0, uint32_t b1, uint32_t b2,
+                                                           uint32_t b3, uint32_t rr, uint32_t ctr2, uint32_t k0,
+                                                           uint32_t k1, uint32_t thi4, uint32_t thi5, uint32_t thi6,
+                                                           uint64_t T4, uint64_t T5, uint64_t T6)
+{
+    const uint32_t w[8] = {a0, a1, a2, a3, b0, b1, b2, b3};
+    uint32_t racc = 0;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int x = 2 * m + par, b = 16 * hh + x;
+            if (!((cand >> b) & 1u)) continue;
+            const uint32_t word = w[4 * hh + (m >> 1)];
+            const uint32_t u = (m & 1) ? (word >> 16) : (word & 0xFFFFu);
+            const int cls = 4 + (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
+            const uint32_t thi = cls == 4 ? thi4 : (cls == 5 ? thi5 : thi6);
+            const uint64_t T = cls == 4 ? T4 : (cls == 5 ? T5 : T6);
+            bool a;
+            if (u != thi) a = u < thi;
+            else a = tie_accept(u, T, (uint32_t)(ibase + hh * istep + x), rr, ctr2, k0, k1);
+            racc |= (uint32_t)a << b;
+        }
+    }
+    return racc;
+}
+
 template <int L, int LPR>
 struct FastLayout {
     static constexpr int NR = L * L;
@@ -328,8 +360,14 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
         if (tie) {
             const uint32_t cand = c2 & colmask;
             const int rA = yy + L * z;  // the high row is rA + L/2
-            const uint32_t racc = resolve_rows(c0, c1, cand, par, 2, H, rA * H, Y * H, L * rA, L * Y, c.rr, c.ctr2,
-                                               c.k0, c.k1, th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
+            uint32_t racc;
+            if constexpr (H == 8)  // each row's half-sites are the whole of calls rndA and rndB
+                racc = resolve_pair_words(c0, c1, cand, par, L * rA, L * Y, rndA.x, rndA.y, rndA.z, rndA.w, rndB.x,
+                                          rndB.y, rndB.z, rndB.w, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5,
+                                          th.thi6, th.T4, th.T5, th.T6);
+            else
+                racc = resolve_rows(c0, c1, cand, par, 2, H, rA * H, Y * H, L * rA, L * Y, c.rr, c.ctr2, c.k0, c.k1,
+                                    th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
             flip = colmask & (~c2 | racc);
         }
         if (!c.valid) flip = 0;
