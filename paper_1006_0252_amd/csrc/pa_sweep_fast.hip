@@ -35,9 +35,9 @@ struct FastThr {
 
 // exact random-acceptance mask of the candidate sites (c >= 4) of nh rows held in the 16-bit
 // halves of the words c0, c1, cand (nh = 2: the second row's half-sites start hstep and its sites
-// istep further on).  The thresholds come as scalars: a structure passed by value to this
-// out-of-line call would go through private (scratch) memory.
-static __device__ __noinline__ uint32_t resolve_rows(uint32_t c0, uint32_t c1, uint32_t cand, int par, int nh, int H,
+// istep further on, its colour has x parity parh).  The thresholds come as scalars: a structure
+// passed by value to this out-of-line call would go through private (scratch) memory.
+static __device__ __noinline__ uint32_t resolve_rows(uint32_t c0, uint32_t c1, uint32_t cand, int par, int parh, int nh, int H,
                                                      int hbase, int hstep, int ibase, int istep, uint32_t rr,
                                                      uint32_t ctr2, uint32_t k0, uint32_t k1, uint32_t thi4,
                                                      uint32_t thi5, uint32_t thi6, uint64_t T4, uint64_t T5, uint64_t T6)
@@ -45,7 +45,7 @@ static __device__ __noinline__ uint32_t resolve_rows(uint32_t c0, uint32_t c1, u
     uint32_t racc = 0;
     for (int hh = 0; hh < nh; ++hh) {
         for (int m = 0; m < H; ++m) {
-            const int x = 2 * m + par, b = 16 * hh + x;
+            const int x = 2 * m + (hh ? parh : par), b = 16 * hh + x;
             if (!((cand >> b) & 1u)) continue;
             const int h = hbase + hh * hstep + m;
             const uint4v v = philox10((uint32_t)(h >> 3), rr, ctr2, kTagMet, k0, k1);
@@ -98,9 +98,8 @@ template <int L, int LPR>
 struct FastLayout {
     static constexpr int NR = L * L;
     static constexpr int H = L / 2;
-    // L = 0 mod 4: rows y and y + L/2 of a plane share one 32-bit word (low and high half)
-    static constexpr bool PAIRED = L % 4 == 0;
-    static constexpr int JROWS = PAIRED ? L / 2 : L;            // coupling-mask entries per plane
+    // rows y and y + L/2 of a plane share one 32-bit word (low and high half)
+    static constexpr int JROWS = L / 2;                         // coupling-mask entries per plane
     static constexpr int RPW = 64 / LPR;
     static constexpr int PL = L / LPR;                          // planes per lane
     static constexpr int PADW = LPR == 4 ? 8 : 0;               // u16 padding per plane (bank stagger)
@@ -155,9 +154,9 @@ __device__ void build_jtab(const pa_state* st, uint32_t* jtab, const FastThr& th
     const int8_t* J = st->J;
     for (int e_i = tid; e_i < L * F::JROWS; e_i += nthr) {
         const int z = e_i / F::JROWS, y = e_i % F::JROWS;
-        uint32_t m[6], mh[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t m[6], mh[6];
         row_masks<L>(J, y + L * z, m);
-        if (F::PAIRED) row_masks<L>(J, y + L / 2 + L * z, mh);
+        row_masks<L>(J, y + L / 2 + L * z, mh);
         uint32_t* e = jtab + z * F::JSTRIDE + y * 8;
         for (int k = 0; k < 6; ++k) e[k] = m[k] | (mh[k] << 16);
         e[6] = 0;
@@ -184,86 +183,12 @@ __device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2
     c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
 }
 
-// one colour of one plane z of this lane's replica, L = 2 mod 4 (one row per word; the half-
-// sites of a colour per row are odd in number, so each site takes its own 16-bit field)
+// one colour of one plane z of this lane's replica: rows y and y + L/2 (not neighbours for L >= 6,
+// nor for L = 4) sit in the low and high half of one 32-bit word, so one bit-sliced count serves
+// both.  The y + 1 word of the last pair and the y - 1 word of the first are the first and last
+// pair with halves swapped.  With L/2 odd the high row's colour has the other x parity.  PH: the
+// position of the plane's first half-site in its Philox call (0 when L = 0 mod 4).
 template <int L, int LPR, int MODE, int PH>
-__device__ __forceinline__ void plane_update(uint16_t* rows, const uint32_t* jtab, int z, int q, int col,
-                                             const PlaneCtx& c, const FastThr& th)
-{
-    using F = FastLayout<L, LPR>;
-    constexpr int H = F::H, RPW = F::RPW, PSTRIDE = F::PSTRIDE;
-    constexpr uint32_t MASK = (1u << L) - 1u;
-    const int zp = (z + 1 == L) ? 0 : z + 1;
-    const int zm = (z == 0) ? L - 1 : z - 1;
-    uint16_t* P0 = rows + z * PSTRIDE + q;
-    const uint16_t* Pp = rows + zp * PSTRIDE + q;
-    const uint16_t* Pm = rows + zm * PSTRIDE + q;
-    const uint32_t* JT = jtab + z * F::JSTRIDE;
-    const uint32_t cb = (uint32_t)((z * (L * H)) >> 3);  // Philox call holding the plane's first half-site
-    const int p0 = (col + z) & 1;                        // x parity of colour col at y = 0
-    const uint32_t cmA = (p0 ? 0xAAAAAAAAu : 0x55555555u) & MASK;
-    const uint32_t cmB = (~cmA) & MASK;
-    const uint32_t thi4 = th.thi4;
-    uint4v rnd = {0, 0, 0, 0};
-#pragma unroll
-    for (int y = 0; y < L; ++y) {
-        const uint32_t own = P0[y * RPW];
-        const uint32_t yp = P0[((y + 1) % L) * RPW];
-        const uint32_t ym = P0[((y + L - 1) % L) * RPW];
-        const uint32_t zpv = Pp[y * RPW];
-        const uint32_t zmv = Pm[y * RPW];
-        const uint32_t* jr = JT + y * 8;
-        const uint32_t dup = own | (own << L);
-        uint32_t c0, c1, c2;
-        bond_count(own ^ (dup >> 1) ^ jr[0], own ^ yp ^ jr[1], own ^ zpv ^ jr[2], own ^ (dup >> (L - 1)) ^ jr[3],
-                   own ^ ym ^ jr[4], own ^ zmv ^ jr[5], c0, c1, c2);
-        const uint32_t colmask = (y & 1) ? cmB : cmA;
-        const int par = p0 ^ (y & 1);
-        uint32_t acc = 0;
-        bool tie = false;
-#pragma unroll
-        for (int m = 0; m < H; ++m) {
-            const int hm = PH + y * H + m;  // position counted from the start of call cb
-            if (hm % 8 == 0 || (y == 0 && m == 0))
-                rnd = philox10(cb + (uint32_t)(hm / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-            const uint32_t u = field16(rnd, hm & 7);
-            const int xb = 2 * m + par;
-            if (MODE == 2) {
-                tie |= (u == 0u);
-            } else if (MODE == 1) {
-                acc |= (uint32_t)(u < thi4) << xb;
-                tie |= (u == thi4) | (u == 0u);
-            } else {
-                // class bits at x as 0 / -1 masks select the threshold (class 4 + c0 + 2 c1; c0 and
-                // c1 are never both set at a candidate site, and non-candidates are masked later)
-                const uint32_t q0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xb, 1);
-                const uint32_t q1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xb, 1);
-                const uint32_t thi = (q1 & th.thi6) | (~q1 & ((q0 & th.thi5) | (~q0 & thi4)));
-                acc |= (uint32_t)(u < thi) << xb;
-                tie |= (u == thi);
-            }
-        }
-        uint32_t flip;
-        if (MODE == 2) flip = colmask & ~c2;
-        else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
-        else flip = colmask & (~c2 | acc);
-        if (tie) {
-            const uint32_t cand = c2 & colmask;
-            const int rho = y + L * z;
-            const uint32_t racc = resolve_rows(c0, c1, cand, par, 1, H, rho * H, 0, L * rho, 0, c.rr, c.ctr2, c.k0,
-                                               c.k1, th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
-            flip = colmask & (~c2 | racc);
-        }
-        if (!c.valid) flip = 0;
-        P0[y * RPW] = (uint16_t)(own ^ flip);
-    }
-}
-
-// one colour of one plane z of this lane's replica, L = 0 mod 4: rows y and y + L/2 (same colour
-// pattern, not neighbours) sit in the low and high half of one 32-bit word, so one bit-sliced
-// count serves both.  The y + 1 word of the last pair and the y - 1 word of the first are the
-// first and last pair with halves swapped.
-template <int L, int LPR, int MODE>
 __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint32_t* jtab, int z, int q, int col,
                                                    const PlaneCtx& c, const FastThr& th)
 {
@@ -282,8 +207,11 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
     const uint32_t* TT = jtab + F::JDWORDS;               // the pair-threshold table
     const uint32_t cb = (uint32_t)((z * (L * H)) >> 3);  // Philox call of the plane's first half-site
     const int p0 = (col + z) & 1;                        // x parity of colour col at even y
-    const uint32_t cmA = (p0 ? 0xAAAAAAAAu : 0x55555555u) & MASKP;
-    const uint32_t cmB = (p0 ? 0x55555555u : 0xAAAAAAAAu) & MASKP;
+    // colour masks of the word for even and odd yy (halves: rows yy and yy + L/2)
+    const uint32_t m0 = (p0 ? 0xAAAAu : 0x5555u) & MASK, m1 = (p0 ? 0x5555u : 0xAAAAu) & MASK;
+    const uint32_t cmA = m0 | ((Y % 2 ? m1 : m0) << 16);
+    const uint32_t cmB = m1 | ((Y % 2 ? m0 : m1) << 16);
+    static_assert(H % 2 == 1 || PH == 0, "paired fields need the plane to start a Philox call");
     const u16x2 t4 = {(uint16_t)th.thi4, (uint16_t)th.thi4};
     const u16x2 one = {1, 1};
     uint4v rndA = {0, 0, 0, 0}, rndB = {0, 0, 0, 0};
@@ -305,70 +233,115 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                    own ^ zmv ^ jr[5], c0, c1, c2);
         const uint32_t colmask = (yy & 1) ? cmB : cmA;
         const int par = p0 ^ (yy & 1);
-        // sites m and m + 1 (m even) of a row take the two 16-bit fields of one Philox word:
-        // both are compared with packed 16-bit ops against their thresholds t (thi4 for c = 4
-        // and 0 above in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per
-        // half: t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept
-        // bits are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved
-        // to 2m + 2 + par.
-        u16x2 zmin = {0xFFFF, 0xFFFF};
-        uint32_t rawA = 0, rawB = 0;
-        // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
-        // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par (+ 16).  With
-        // L = 16 the c1 bit of the high row's x = 15 would leave the word: that row takes c1(x)
-        // at bit x and c0(x) at bit x - 1 instead (the same nibble, one bit lower)
-        const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
-        const uint32_t c01h = L == 16 ? ((c1 & colmask) | ((c0 >> 1) & ~colmask)) : c01;
-        constexpr int OFFH = L == 16 ? 15 : 16;
-#pragma unroll
-        for (int m = 0; m < H; m += 2) {
-            const int hA = yy * H + m, hB = (yy + Y) * H + m;  // half-site positions from call cb
-            if (hA % 8 == 0 || (yy == 0 && m == 0))
-                rndA = philox10(cb + (uint32_t)(hA / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-            if (hB % 8 == 0 || (yy == 0 && m == 0))
-                rndB = philox10(cb + (uint32_t)(hB / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-            const u16x2 wA = __builtin_bit_cast(u16x2, word_of(rndA, (hA & 7) >> 1));
-            const u16x2 wB = __builtin_bit_cast(u16x2, word_of(rndB, (hB & 7) >> 1));
-            if (MODE == 2) {
-                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
-            } else {
-                const u16x2 tA = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
-                const u16x2 tB = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01h >> (OFFH + 2 * m + par)) & 15u]);
-                const u16x2 dA = __builtin_elementwise_sub_sat(tA, wA);
-                const u16x2 dB = __builtin_elementwise_sub_sat(tB, wB);
-                // min(d, 1) per half, written out: as an expression the optimiser turns it into
-                // d != 0, i.e. two compares, two selects and a byte permute per word
-                uint32_t aA, aB;
-                asm("v_pk_min_u16 %0, %1, %2" : "=v"(aA) : "v"(dA), "v"(one));
-                asm("v_pk_min_u16 %0, %1, %2" : "=v"(aB) : "v"(dB), "v"(one));
-                rawA |= aA << (2 * m + par);
-                rawB |= aB << (2 * m + par);
-                if (MODE == 1)
-                    zmin = __builtin_elementwise_min(
-                        zmin, __builtin_elementwise_min(__builtin_elementwise_min(wA - tA, wA),
-                                                        __builtin_elementwise_min(wB - tB, wB)));
-                else
-                    zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA - tA, wB - tB));
-            }
-        }
-        const bool tie = zmin.x == 0 || zmin.y == 0;
-        const uint32_t acc = (rawA & 0xFFFFu) | (rawA >> 14) | (((rawB & 0xFFFFu) | (rawB >> 14)) << 16);
         uint32_t flip;
-        if (MODE == 2) flip = colmask & ~c2;
-        else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
-        else flip = colmask & (~c2 | acc);
-        if (tie) {
-            const uint32_t cand = c2 & colmask;
-            const int rA = yy + L * z;  // the high row is rA + L/2
-            uint32_t racc;
-            if constexpr (H == 8)  // each row's half-sites are the whole of calls rndA and rndB
-                racc = resolve_pair_words(c0, c1, cand, par, L * rA, L * Y, rndA.x, rndA.y, rndA.z, rndA.w, rndB.x,
-                                          rndB.y, rndB.z, rndB.w, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5,
-                                          th.thi6, th.T4, th.T5, th.T6);
-            else
-                racc = resolve_rows(c0, c1, cand, par, 2, H, rA * H, Y * H, L * rA, L * Y, c.rr, c.ctr2, c.k0, c.k1,
-                                    th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
-            flip = colmask & (~c2 | racc);
+        if constexpr (H % 2 == 0) {
+            // sites m and m + 1 (m even) of a row take the two 16-bit fields of one Philox word:
+            // both are compared with packed 16-bit ops against their thresholds t (thi4 for c = 4
+            // and 0 above in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per
+            // half: t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept
+            // bits are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved
+            // to 2m + 2 + par.
+            u16x2 zmin = {0xFFFF, 0xFFFF};
+            uint32_t rawA = 0, rawB = 0;
+            // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
+            // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par (+ 16).  With
+            // L = 16 the c1 bit of the high row's x = 15 would leave the word: that row takes c1(x)
+            // at bit x and c0(x) at bit x - 1 instead (the same nibble, one bit lower)
+            const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
+            const uint32_t c01h = L == 16 ? ((c1 & colmask) | ((c0 >> 1) & ~colmask)) : c01;
+            constexpr int OFFH = L == 16 ? 15 : 16;
+    #pragma unroll
+            for (int m = 0; m < H; m += 2) {
+                const int hA = PH + yy * H + m, hB = PH + (yy + Y) * H + m;  // half-site positions from call cb
+                if (hA % 8 == 0 || (yy == 0 && m == 0))
+                    rndA = philox10(cb + (uint32_t)(hA / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                if (hB % 8 == 0 || (yy == 0 && m == 0))
+                    rndB = philox10(cb + (uint32_t)(hB / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                const u16x2 wA = __builtin_bit_cast(u16x2, word_of(rndA, (hA & 7) >> 1));
+                const u16x2 wB = __builtin_bit_cast(u16x2, word_of(rndB, (hB & 7) >> 1));
+                if (MODE == 2) {
+                    zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
+                } else {
+                    const u16x2 tA = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
+                    const u16x2 tB = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01h >> (OFFH + 2 * m + par)) & 15u]);
+                    const u16x2 dA = __builtin_elementwise_sub_sat(tA, wA);
+                    const u16x2 dB = __builtin_elementwise_sub_sat(tB, wB);
+                    // min(d, 1) per half, written out: as an expression the optimiser turns it into
+                    // d != 0, i.e. two compares, two selects and a byte permute per word
+                    uint32_t aA, aB;
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(aA) : "v"(dA), "v"(one));
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(aB) : "v"(dB), "v"(one));
+                    rawA |= aA << (2 * m + par);
+                    rawB |= aB << (2 * m + par);
+                    if (MODE == 1)
+                        zmin = __builtin_elementwise_min(
+                            zmin, __builtin_elementwise_min(__builtin_elementwise_min(wA - tA, wA),
+                                                            __builtin_elementwise_min(wB - tB, wB)));
+                    else
+                        zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA - tA, wB - tB));
+                }
+            }
+            const bool tie = zmin.x == 0 || zmin.y == 0;
+            const uint32_t acc = (rawA & 0xFFFFu) | (rawA >> 14) | (((rawB & 0xFFFFu) | (rawB >> 14)) << 16);
+            if (MODE == 2) flip = colmask & ~c2;
+            else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+            else flip = colmask & (~c2 | acc);
+            if (tie) {
+                const uint32_t cand = c2 & colmask;
+                const int rA = yy + L * z;  // the high row is rA + L/2
+                uint32_t racc;
+                if constexpr (H == 8)  // each row's half-sites are the whole of calls rndA and rndB
+                    racc = resolve_pair_words(c0, c1, cand, par, L * rA, L * Y, rndA.x, rndA.y, rndA.z, rndA.w, rndB.x,
+                                              rndB.y, rndB.z, rndB.w, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5,
+                                              th.thi6, th.T4, th.T5, th.T6);
+                else
+                    racc = resolve_rows(c0, c1, cand, par, par, 2, H, rA * H, Y * H, L * rA, L * Y, c.rr, c.ctr2, c.k0,
+                                        c.k1, th.thi4, th.thi5, th.thi6, th.T4, th.T5, th.T6);
+                flip = colmask & (~c2 | racc);
+            }
+        } else {
+            // an odd number of half-sites per row: each site takes its own 16-bit field
+            const int parh = par ^ (Y & 1);  // x parity of the high row's colour
+            uint32_t acc = 0;
+            bool tie = false;
+#pragma unroll
+            for (int m = 0; m < H; ++m) {
+                const int hA = PH + yy * H + m, hB = PH + (yy + Y) * H + m;
+                if (hA % 8 == 0 || (yy == 0 && m == 0))
+                    rndA = philox10(cb + (uint32_t)(hA / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                if (hB % 8 == 0 || (yy == 0 && m == 0))
+                    rndB = philox10(cb + (uint32_t)(hB / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                const uint32_t uA = field16(rndA, hA & 7), uB = field16(rndB, hB & 7);
+                const int xA = 2 * m + par, xB = 16 + 2 * m + parh;
+                if (MODE == 2) {
+                    tie |= (uA == 0u) | (uB == 0u);
+                } else if (MODE == 1) {
+                    acc |= ((uint32_t)(uA < th.thi4) << xA) | ((uint32_t)(uB < th.thi4) << xB);
+                    tie |= (uA == th.thi4) | (uA == 0u) | (uB == th.thi4) | (uB == 0u);
+                } else {
+                    // class bits at x as 0 / -1 masks select the threshold (class 4 + c0 + 2 c1; c0
+                    // and c1 are never both set at a candidate site, non-candidates are masked later)
+                    const uint32_t qA0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xA, 1);
+                    const uint32_t qA1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xA, 1);
+                    const uint32_t qB0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xB, 1);
+                    const uint32_t qB1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xB, 1);
+                    const uint32_t tA = (qA1 & th.thi6) | (~qA1 & ((qA0 & th.thi5) | (~qA0 & th.thi4)));
+                    const uint32_t tB = (qB1 & th.thi6) | (~qB1 & ((qB0 & th.thi5) | (~qB0 & th.thi4)));
+                    acc |= ((uint32_t)(uA < tA) << xA) | ((uint32_t)(uB < tB) << xB);
+                    tie |= (uA == tA) | (uB == tB);
+                }
+            }
+            if (MODE == 2) flip = colmask & ~c2;
+            else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+            else flip = colmask & (~c2 | acc);
+            if (tie) {
+                const uint32_t cand = c2 & colmask;
+                const int rA = yy + L * z;  // the high row is rA + L/2
+                const uint32_t racc = resolve_rows(c0, c1, cand, par, parh, 2, H, rA * H, Y * H, L * rA,
+                                                   L * Y, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5, th.thi6, th.T4,
+                                                   th.T5, th.T6);
+                flip = colmask & (~c2 | racc);
+            }
         }
         if (!c.valid) flip = 0;
         P0[yy * RPW] = own ^ flip;
@@ -382,7 +355,7 @@ template <int L, int LPR>
 __device__ __forceinline__ int row_slot(int y)
 {
     using F = FastLayout<L, LPR>;
-    return F::PAIRED ? 2 * (y % (L / 2)) * F::RPW + y / (L / 2) : y * F::RPW;
+    return 2 * (y % (L / 2)) * F::RPW + y / (L / 2);
 }
 
 // The rows of the 64 replicas of bit-packed group g (two bytes per row and replica) between HBM
@@ -405,7 +378,7 @@ __device__ void group_rows_io(const pa_state* st, int64_t g, uint16_t* rows0, in
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 4 * k + i, w = r / RPW, qq = r % RPW;
-            slot[i] = P + w * (F::ROW_BYTES / 2) + (F::PAIRED ? 2 * qq : qq);
+            slot[i] = P + w * (F::ROW_BYTES / 2) + 2 * qq;
         }
         if (!STORE) {
             const uint64_t v = G[e];
@@ -455,7 +428,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll 1
     for (int t = 0; t < (IO ? PL : 0); ++t) {
         const int z = j * PL + t;
-        uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
+        uint16_t* P = rows + z * PSTRIDE + 2 * q;
         for (int y = 0; y < L; ++y) {
             const int rho = y + L * z;
             uint32_t v = 0;
@@ -482,14 +455,15 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
             c.ctr2 = (uint32_t)(2 * t_sweep + col);
             for (int t = 0; t < PL; ++t) {
                 const int z = j * PL + t;
-                if constexpr (F::PAIRED) {
-                    plane_update_pairs<L, LPR, MODE>(reinterpret_cast<uint32_t*>(rows), jtab, z, q, col, c, th);
+                uint32_t* rows32 = reinterpret_cast<uint32_t*>(rows);
+                if constexpr (L % 4 == 0) {
+                    plane_update_pairs<L, LPR, MODE, 0>(rows32, jtab, z, q, col, c, th);
                 } else {
                     switch ((z * (L * H)) & 7) {
-                        case 0: plane_update<L, LPR, MODE, 0>(rows, jtab, z, q, col, c, th); break;
-                        case 2: plane_update<L, LPR, MODE, 2>(rows, jtab, z, q, col, c, th); break;
-                        case 4: plane_update<L, LPR, MODE, 4>(rows, jtab, z, q, col, c, th); break;
-                        default: plane_update<L, LPR, MODE, 6>(rows, jtab, z, q, col, c, th); break;
+                        case 0: plane_update_pairs<L, LPR, MODE, 0>(rows32, jtab, z, q, col, c, th); break;
+                        case 2: plane_update_pairs<L, LPR, MODE, 2>(rows32, jtab, z, q, col, c, th); break;
+                        case 4: plane_update_pairs<L, LPR, MODE, 4>(rows32, jtab, z, q, col, c, th); break;
+                        default: plane_update_pairs<L, LPR, MODE, 6>(rows32, jtab, z, q, col, c, th); break;
                     }
                 }
             }
@@ -504,35 +478,21 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
         const int z = j * PL + t;
         const int zp = (z + 1 == L) ? 0 : z + 1;
         const uint32_t* JT = jtab + z * F::JSTRIDE;
-        if constexpr (F::PAIRED) {
-            constexpr int Y = L / 2, PS = PSTRIDE / 2;
-            constexpr uint32_t MASKP = MASK | (MASK << 16);
-            constexpr uint32_t XP = (MASK >> 1) | ((MASK >> 1) << 16);
-            const uint32_t* P0 = reinterpret_cast<const uint32_t*>(rows) + z * PS + q;
-            const uint32_t* Pp = reinterpret_cast<const uint32_t*>(rows) + zp * PS + q;
+        constexpr int Y = L / 2, PS = PSTRIDE / 2;
+        constexpr uint32_t MASKP = MASK | (MASK << 16);
+        constexpr uint32_t XP = (MASK >> 1) | ((MASK >> 1) << 16);
+        const uint32_t* P0 = reinterpret_cast<const uint32_t*>(rows) + z * PS + q;
+        const uint32_t* Pp = reinterpret_cast<const uint32_t*>(rows) + zp * PS + q;
 #pragma unroll
-            for (int yy = 0; yy < Y; ++yy) {
-                const uint32_t own = P0[yy * RPW];
-                uint32_t yp = P0[((yy + 1) % Y) * RPW];
-                if (yy == Y - 1) yp = (yp >> 16) | (yp << 16);
-                const uint32_t rp = ((own >> 1) & XP) | ((own << (L - 1)) & ~XP);
-                const uint32_t* jr = JT + yy * 8;
-                neg += __popc((own ^ rp ^ jr[0]) & MASKP);
-                neg += __popc((own ^ yp ^ jr[1]) & MASKP);
-                neg += __popc((own ^ Pp[yy * RPW] ^ jr[2]) & MASKP);
-            }
-        } else {
-            const uint16_t* P0 = rows + z * PSTRIDE + q;
-            const uint16_t* Pp = rows + zp * PSTRIDE + q;
-#pragma unroll
-            for (int y = 0; y < L; ++y) {
-                const uint32_t own = P0[y * RPW];
-                const uint32_t dup = own | (own << L);
-                const uint32_t* jr = JT + y * 8;
-                neg += __popc((own ^ (dup >> 1) ^ jr[0]) & MASK);
-                neg += __popc((own ^ P0[((y + 1) % L) * RPW] ^ jr[1]) & MASK);
-                neg += __popc((own ^ Pp[y * RPW] ^ jr[2]) & MASK);
-            }
+        for (int yy = 0; yy < Y; ++yy) {
+            const uint32_t own = P0[yy * RPW];
+            uint32_t yp = P0[((yy + 1) % Y) * RPW];
+            if (yy == Y - 1) yp = (yp >> 16) | (yp << 16);
+            const uint32_t rp = ((own >> 1) & XP) | ((own << (L - 1)) & ~XP);
+            const uint32_t* jr = JT + yy * 8;
+            neg += __popc((own ^ rp ^ jr[0]) & MASKP);
+            neg += __popc((own ^ yp ^ jr[1]) & MASKP);
+            neg += __popc((own ^ Pp[yy * RPW] ^ jr[2]) & MASKP);
         }
     }
     for (int off = RPW; off < 64; off <<= 1) neg += __shfl_xor(neg, off, 64);
@@ -545,7 +505,7 @@ __device__ __forceinline__ void sweep_tile(const pa_state* st, int64_t rbase, co
 #pragma unroll 1
         for (int t = 0; t < (IO ? PL : 0); ++t) {
             const int z = j * PL + t;
-            const uint16_t* P = rows + z * PSTRIDE + (F::PAIRED ? 2 * q : q);
+            const uint16_t* P = rows + z * PSTRIDE + 2 * q;
             for (int y = 0; y < L; ++y) {
                 const int rho = y + L * z;
                 const uint32_t v = P[row_slot<L, LPR>(y)];

@@ -98,18 +98,21 @@ def test_sweep_parity(dim, L, layout, R0):
         assert np.array_equal(E, Eo), f"energies differ at beta={beta}"
 
 
-@pytest.mark.parametrize("L,layout", [(16, "bits64"), (10, "bits64"), (8, "u8"), (12, "u8")])
-def test_sweep_launch_shapes_agree(L, layout):
-    # every launch shape (lanes per replica, waves per block) gives the same sample
+@pytest.mark.parametrize("L,layout,cap", [(16, "bits64", None), (16, "bits64", 640), (10, "bits64", None), (8, "u8", None),
+                                          (12, "u8", None)])
+def test_sweep_launch_shapes_agree(L, layout, cap):
+    # every launch shape (lanes per replica, waves per block) gives the same sample; shapes whose
+    # block holds one whole 64-replica group move it block-wide, and with capacity 640 whole
+    # blocks lie past the population
     R0 = 200
     J = o.couplings(3, L, 3)
     so, Eo = o.init_population(3, L, J, 7, R0)
     o.sweep(3, L, J, 7, 0.8, R0, so, Eo, 0, 3)
     try:
-        for lpr, wpb in ((1, 1), (1, 4), (2, 2), (2, 4), (4, 1), (4, 3)):
+        for lpr, wpb in ((1, 1), (1, 4), (2, 2), (2, 4), (4, 1), (4, 3), (4, 4)):
             note(f"sweep shape L={L} {layout} lpr={lpr} wpb={wpb}")
             pa.set_sweep_config(lpr, wpb)
-            run = make_run(3, L, R0, layout)
+            run = make_run(3, L, R0, layout, capacity=cap)
             sched = pa.Schedule([0.0, 0.8], 3, run.n_bins, device=DEV)
             run.sweep(sched.step(1))
             s, E = run.population()
