@@ -42,9 +42,10 @@ CHAINS = {
 
 
 def ring_ensemble(disorder_seed, M, R0=1000, n_temps=51, n_sweeps=5, device="cuda", N=64, couplings="pm1",
-                  betas=None):
+                  betas=None, graph=True):
     """M runs of one ring realization; returns (-beta F~ [M][n_temps], E mean [M][n_temps], betas,
-    couplings, seconds, attempts)."""
+    couplings, seconds, attempts).  graph: the schedule is captured once as one HIP graph and the
+    seconds are those of its replay (the same kernels, hence the same sample, as stepping eagerly)."""
     import torch
 
     betas = pa.linear_schedule(n_temps) if betas is None else np.asarray(betas, np.float64)
@@ -54,10 +55,14 @@ def ring_ensemble(disorder_seed, M, R0=1000, n_temps=51, n_sweeps=5, device="cud
     batch = pa.Batch(specs, n_temps, layout="u8", device=device)
     batch.init()
     sched = pa.Schedule(betas, n_sweeps, batch.runs[0].n_bins, device=device)
+    g = batch.capture(sched, range(1, n_temps)) if graph else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(1, n_temps):
-        batch.step(sched, k)
+    if graph:
+        g.launch()
+    else:
+        for k in range(1, n_temps):
+            batch.step(sched, k)
     batch.stream.synchronize()
     T = time.perf_counter() - t0
     code, flags = batch.status()

@@ -84,3 +84,15 @@ def test_gaussian_chain_bias_reduced():
         assert abs(p["F_w"] - p["F_exact"]) < 4 * p["F_w_err"] + 0.02
         assert abs(p["E_w"] - p["E_exact"]) < 4 * p["E_w_err"] + 0.05
         assert p["var"] > 0
+
+
+@pytest.mark.parametrize("couplings,N", [("pm1", 64), ("gauss", 256)])
+def test_chain_ensemble_graph_equals_eager(couplings, N):
+    # the chain ensembles are timed as one captured HIP graph: its replay gives the records of
+    # stepping eagerly, bit for bit
+    note(f"chain ensemble graph vs eager {couplings} N={N}")
+    betas = np.linspace(0.0, 2.0, 9)
+    kw = dict(R0=300, n_sweeps=3, device=DEV, N=N, couplings=couplings, betas=betas)
+    Xg, Eg, _, _, _, ag = bias.ring_ensemble(3, 6, graph=True, **kw)
+    Xe, Ee, _, _, _, ae = bias.ring_ensemble(3, 6, graph=False, **kw)
+    assert np.array_equal(Xg, Xe) and np.array_equal(Eg, Ee) and ag == ae
