@@ -300,10 +300,16 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                 flip = colmask & (~c2 | racc);
             }
         } else {
-            // an odd number of half-sites per row: each site takes its own 16-bit field
+            // an odd number of half-sites per row, so fields do not pair within a row; but Y H is
+            // odd, so site m of the low row and site m of the high row sit in opposite halves of
+            // their words: one bit-field insert puts u_A in the low and u_B in the high half, and
+            // the pair is compared with the packed ops above.  The high row's accept bits land at
+            // 16 + 2m + par and move to its own parity parh at the end.
             const int parh = par ^ (Y & 1);  // x parity of the high row's colour
-            uint32_t acc = 0;
-            bool tie = false;
+            u16x2 zmin = {0xFFFF, 0xFFFF};
+            uint32_t raw = 0;
+            // MODE 0: c0(x) at bit x and c1(x) at bit x + 1 for the colour's sites of both rows
+            const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
 #pragma unroll
             for (int m = 0; m < H; ++m) {
                 const int hA = PH + yy * H + m, hB = PH + (yy + Y) * H + m;
@@ -311,26 +317,26 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                     rndA = philox10(cb + (uint32_t)(hA / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
                 if (hB % 8 == 0 || (yy == 0 && m == 0))
                     rndB = philox10(cb + (uint32_t)(hB / 8), c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-                const uint32_t uA = field16(rndA, hA & 7), uB = field16(rndB, hB & 7);
-                const int xA = 2 * m + par, xB = 16 + 2 * m + parh;
+                const uint32_t wa = word_of(rndA, (hA & 7) >> 1), wb = word_of(rndB, (hB & 7) >> 1);
+                static_assert(((Y * H) & 1) == 1, "the two rows' fields of site m sit in opposite halves");
+                const uint32_t wv = (hA & 1) ? __builtin_amdgcn_alignbit(wb, wa, 16) : ((wa & 0xFFFFu) | (wb & 0xFFFF0000u));
+                const u16x2 w = __builtin_bit_cast(u16x2, wv);
                 if (MODE == 2) {
-                    tie |= (uA == 0u) | (uB == 0u);
-                } else if (MODE == 1) {
-                    acc |= ((uint32_t)(uA < th.thi4) << xA) | ((uint32_t)(uB < th.thi4) << xB);
-                    tie |= (uA == th.thi4) | (uA == 0u) | (uB == th.thi4) | (uB == 0u);
+                    zmin = __builtin_elementwise_min(zmin, w);
                 } else {
-                    // class bits at x as 0 / -1 masks select the threshold (class 4 + c0 + 2 c1; c0
-                    // and c1 are never both set at a candidate site, non-candidates are masked later)
-                    const uint32_t qA0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xA, 1);
-                    const uint32_t qA1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xA, 1);
-                    const uint32_t qB0 = (uint32_t)__builtin_amdgcn_sbfe((int)c0, xB, 1);
-                    const uint32_t qB1 = (uint32_t)__builtin_amdgcn_sbfe((int)c1, xB, 1);
-                    const uint32_t tA = (qA1 & th.thi6) | (~qA1 & ((qA0 & th.thi5) | (~qA0 & th.thi4)));
-                    const uint32_t tB = (qB1 & th.thi6) | (~qB1 & ((qB0 & th.thi5) | (~qB0 & th.thi4)));
-                    acc |= ((uint32_t)(uA < tA) << xA) | ((uint32_t)(uB < tB) << xB);
-                    tie |= (uA == tA) | (uB == tB);
+                    const int xA = 2 * m + par, xB = 16 + 2 * m + parh;
+                    const u16x2 t = MODE == 1 ? t4
+                                              : __builtin_bit_cast(u16x2, TT[((c01 >> xA) & 3u) | (((c01 >> xB) & 3u) << 2)]);
+                    const u16x2 d = __builtin_elementwise_sub_sat(t, w);
+                    uint32_t a;  // min(d, 1) per half, written out (see above)
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(a) : "v"(d), "v"(one));
+                    raw |= a << (2 * m + par);
+                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t, w));
+                    else zmin = __builtin_elementwise_min(zmin, w - t);
                 }
             }
+            const bool tie = zmin.x == 0 || zmin.y == 0;
+            const uint32_t acc = (raw & 0xFFFFu) | ((raw >> (16 + par)) << (16 + parh));
             if (MODE == 2) flip = colmask & ~c2;
             else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
             else flip = colmask & (~c2 | acc);

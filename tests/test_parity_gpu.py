@@ -45,7 +45,7 @@ INIT_CASES = [
     (1, 64, "u8", 150), (1, 64, "bits64", 150), (1, 100, "u8", 70), (1, 100, "bits64", 70),
     (3, 2, "u8", 100), (3, 2, "bits64", 100), (3, 4, "bits64", 200), (3, 6, "u8", 130), (3, 6, "bits64", 130),
     (3, 8, "u8", 200), (3, 8, "bits64", 200), (3, 10, "bits64", 90), (3, 12, "bits64", 70),
-    (3, 16, "u8", 70), (3, 16, "bits64", 130),
+    (3, 14, "u8", 70), (3, 16, "u8", 70), (3, 16, "bits64", 130),
 ]
 
 
