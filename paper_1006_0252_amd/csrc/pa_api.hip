@@ -410,7 +410,7 @@ int pa_graph_end(void* stream, void** graph_exec)
     if (hipStreamEndCapture((hipStream_t)stream, &g) != hipSuccess || !g) return PA_ERR_HIP;
     hipGraphExec_t e = nullptr;
     const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiated graph does not need it
     if (err != hipSuccess) return PA_ERR_HIP;
     *graph_exec = (void*)e;
     return PA_OK;

@@ -581,7 +581,7 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
     if (consecutive) {
         int64_t cap = 0;
         for (int r = 0; r < n_runs; ++r) cap = runs[r].capacity > cap ? runs[r].capacity : cap;
-        return go(runs[0].state, n_runs, cap, (hipStream_t)runs[0].stream);
+        return go(runs[0].state, n_runs, cap, s);  // s is the runs' common stream
     }
     for (int r = 0; r < n_runs; ++r) {
         const int st = go(runs[r].state, 1, runs[r].capacity, (hipStream_t)runs[r].stream);

@@ -195,7 +195,6 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
     using F = FastLayout<L, LPR>;
     constexpr int H = F::H, Y = L / 2, RPW = F::RPW, PS = F::PSTRIDE / 2;
     constexpr uint32_t MASK = (1u << L) - 1u;
-    constexpr uint32_t MASKP = MASK | (MASK << 16);
     constexpr uint32_t XP = (MASK >> 1) | ((MASK >> 1) << 16);  // x <= L - 2 in each half: x + 1 from w >> 1
     constexpr uint32_t XM = XP << 1;                             // x >= 1: x - 1 from w << 1
     const int zp = (z + 1 == L) ? 0 : z + 1;
