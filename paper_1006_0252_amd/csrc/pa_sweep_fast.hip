@@ -1,24 +1,27 @@
 // Metropolis sweeps of the cube for even L <= 16: the same sample as the generic kernel
 // (same Philox fields, same acceptance rule), laid out for the vector ALU.
 //
-//  - lane = replica; a replica's rows (one 16-bit word per (y, z) row, bit x = spin) sit in
-//    LDS, planes of L rows per z; LPR lanes share a replica by taking L/LPR planes each;
-//  - the y loop of a plane is unrolled, so every neighbour row is an immediate LDS offset, and
-//    the Philox field of every site is a compile-time constant given the plane's phase (the
-//    position of its first half-site inside an 8-site Philox chunk: 0 when L = 0 mod 4,
-//    0/2/4/6 by plane when L = 2 mod 4);
-//  - per row, the six bond words J s s (bit-parallel over x) feed a bit-sliced adder giving
-//    c = number of bonds with J s_i s_j = -1 (dE = 4c - 12); c <= 3 flips outright;
-//  - the 16-bit first look of each site against its threshold is specialised by regime:
-//    MODE 2: every threshold of c >= 4 has top 16 bits 0 (beta > ln 2^16 / 4): only u == 0
-//            can accept, and that is a tie;  MODE 1: only c = 4 has a non-zero top;
-//    MODE 0: general.  Possible ties are flagged per lane and resolved exactly with the
-//    48 low bits in a separate (rare) path;
+//  - lane = replica; a replica's rows (bit x = spin) sit in LDS, rows y and y + L/2 of a plane
+//    as the low and high half of one 32-bit word; LPR lanes share a replica by taking L/LPR
+//    planes each;
+//  - the row-pair loop of a plane is unrolled, so every neighbour word is an immediate LDS
+//    offset, and the Philox field of every site is a compile-time constant given the plane's
+//    phase (the position of its first half-site inside an 8-site Philox chunk: 0 when
+//    L = 0 mod 4, 0/2/4/6 by plane when L = 2 mod 4);
+//  - per row pair, the six bond words J s s (bit-parallel over x, both rows at once) feed a
+//    bit-sliced adder giving c = number of bonds with J s_i s_j = -1 (dE = 4c - 12); c <= 3
+//    flips outright;
+//  - the 16-bit first look is done on pairs of sites with packed 16-bit ops, specialised by
+//    regime:  MODE 2: every threshold of c >= 4 has top 16 bits 0 (beta > ln 2^16 / 4): only
+//    u == 0 can accept, and that is a tie;  MODE 1: only c = 4 has a non-zero top;  MODE 0:
+//    general, the pair's thresholds from a 16-entry LDS table.  Possible ties are flagged per
+//    lane and resolved exactly with the 48 low bits in a separate (rare) path;
 //  - energies are recomputed once per launch from bond popcounts.
 //
 // Two launch forms share the per-tile code: one block of waves per group of replicas of one
-// run (k_sweep3f), and a persistent kernel for a batch of runs (k_sweep_batch), one wave per
-// block pulling (run, tile) items from a device work counter.
+// run (k_sweep3f, which moves whole 64-replica bit-packed groups block-wide when its waves hold
+// one), and a persistent kernel for a batch of runs (k_sweep_batch), one wave per block pulling
+// (run, tile) items from a device work counter.
 #include <string.h>
 
 #include <algorithm>
@@ -136,9 +139,10 @@ __device__ void row_masks(const int8_t* J, int rho, uint32_t m[6])
     }
 }
 
-// the block-shared tables: coupling masks per row (rows y and y + L/2 in one entry when paired);
-// then the thresholds of two consecutive sites of a colour by their class bits: entry
-// a + 4 b (a, b = c0 + 2 c1 of the first and second site) holds thi(a) | thi(b) << 16, with
+// the block-shared tables: coupling masks per row pair (rows y and y + L/2 in one entry);
+// then the thresholds of a pair of sites by their class bits (two consecutive sites of a colour
+// in a row, or site m of both rows of a word when L/2 is odd): entry a + 4 b (a, b = c0 + 2 c1
+// of the first and second site) holds thi(a) | thi(b) << 16, with
 // class index 0, 1, 2 for c = 4, 5, 6 (3 cannot occur at a candidate site).  A threshold of
 // 0x10000 (always accept) is stored as 0xFFFF: every u below it accepts, and u = 0xFFFF equals
 // it, which flags a tie that the exact path settles with the true threshold
