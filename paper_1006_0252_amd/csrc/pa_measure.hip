@@ -98,22 +98,46 @@ __device__ inline int hamming_rows(const pa_state* a, const pa_state* b, int64_t
     return d;
 }
 
-__global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_state* b_given, int pair_xor)
+// Hamming distance of replica j of runs A and B (pair_xor: B is A's partner run in the batch), one
+// thread per replica, kOverlapItems replicas per thread of a block.  The block counts its distances
+// in an LDS histogram (cap entries, when N + 1 fits) and adds its non-zero bins to the run's
+// histogram: the distances of a population sit within a few sqrt(N) of a few values, so one
+// global atomic per replica would serialise on a handful of addresses.
+constexpr int kOverlapItems = 4;
+
+__global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_state* b_given, int pair_xor, int cap)
 {
+    extern __shared__ uint32_t hloc[];
     pa_state* a = base + blockIdx.y;
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
-    if (a->status || b->status) return;
+    if (a->status || b->status) return;  // the same for the whole block
     const int64_t P = min(a->R, b->R);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P) return;
+    const int N = a->N;
     const int n_rows = a->dim == 1 ? (a->N + 31) / 32 : a->L * a->L;
     const int WB = a->dim == 1 ? 4 : (a->L <= 8 ? 1 : (a->L <= 16 ? 2 : 4));
-    int d;
-    if (WB == 1) d = hamming_rows<uint8_t>(a, b, j, n_rows);
-    else if (WB == 2) d = hamming_rows<uint16_t>(a, b, j, n_rows);
-    else d = hamming_rows<uint32_t>(a, b, j, n_rows);
     int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
-    atomicAdd((unsigned long long*)&qh[d], 1ull);
+    const bool local = N + 1 <= cap;
+    if (local) {
+        for (int d = threadIdx.x; d <= N; d += blockDim.x) hloc[d] = 0;
+        __syncthreads();
+    }
+    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x * kOverlapItems;
+    const int64_t j1 = min(P, j0 + (int64_t)blockDim.x * kOverlapItems);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+        int d;
+        if (WB == 1) d = hamming_rows<uint8_t>(a, b, j, n_rows);
+        else if (WB == 2) d = hamming_rows<uint16_t>(a, b, j, n_rows);
+        else d = hamming_rows<uint32_t>(a, b, j, n_rows);
+        if (local) atomicAdd(&hloc[d], 1u);
+        else atomicAdd((unsigned long long*)&qh[d], 1ull);
+    }
+    if (local) {
+        __syncthreads();
+        for (int d = threadIdx.x; d <= N; d += blockDim.x) {
+            const uint32_t c = hloc[d];
+            if (c) atomicAdd((unsigned long long*)&qh[d], (unsigned long long)c);
+        }
+    }
 }
 
 // q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A
@@ -182,9 +206,13 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
         // or the partner's stream joined by the caller
         if (runs[0].layout == PA_U8)
             hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
-        else
-            hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + 255) / 256), n), dim3(256), 0, s, base, bg,
-                               pair_xor);
+        else {
+            // LDS histogram of up to 8192 bins (every cube; longer chains count in global memory)
+            const int cap = N + 1 <= 8192 ? (int)(N + 1) : 0;
+            const int64_t per_block = 256 * kOverlapItems;
+            hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + per_block - 1) / per_block), n), dim3(256),
+                               (size_t)cap * 4, s, base, bg, pair_xor, cap);
+        }
         hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(256), 0, s, base, bg, pair_xor);
     }
     return hip_status(hipGetLastError());
