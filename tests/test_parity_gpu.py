@@ -222,6 +222,26 @@ def test_overlap_parity(dim, L, layout):
         assert close(rec[9], q2) and close(rec[10], q4) and close(rec[11], g)
 
 
+def test_overlap_long_chain_counts_in_global_memory():
+    # a chain of 9000 sites: its N + 1 overlap bins exceed the bit-packed overlap kernel's LDS
+    # histogram, which then counts in global memory; the overlap of the two initial populations
+    # against the oracle's
+    N, RA, RB = 9000, 300, 250
+    note(f"overlap long chain N={N}")
+    a = pa.Run(1, N, RA, 101, 9, n_records=2, layout="bits64", device=DEV).init()
+    b = pa.Run(1, N, RB, 202, 9, n_records=2, layout="bits64", device=DEV).init()
+    pa.measure([a, b], [1, 0])
+    J = o.couplings(1, N, 9)
+    s_a, _ = o.init_population(1, N, J, 101, RA)
+    s_b, _ = o.init_population(1, N, J, 202, RB)
+    h, P = o.overlap_hist(N, s_a, s_b)
+    q2, q4, g = o.overlap_stats(N, h)
+    for run in (a, b):
+        rec = run.records()[0]
+        assert rec[12] == P
+        assert close(rec[9], q2) and close(rec[10], q4) and close(rec[11], g)
+
+
 def test_capacity_and_extinction_flags_leave_state_unchanged():
     dim, L, R0 = 3, 6, 200
     note("capacity overflow")
