@@ -148,3 +148,16 @@ def test_unpack_spins_layouts():
                 words[r // 64, i // rowsites, r % 64] |= np.uint64(int(s[r, i]) << (i % rowsites))
         raw = words.astype(dt).view(np.uint8).reshape(-1)
         assert np.array_equal(pa.unpack_spins(raw, dim, L, pa.PA_BITS64, R, 0), s)
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_bench_refuses_more_than_one_gpu(n):
+    # the benchmark is a one-GPU measurement: asked for more it says so and exits before any GPU work
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", str(n)], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
