@@ -210,8 +210,8 @@ int pa_init_couplings(pa_run* runs, int n_runs, const int8_t* const* J_host);
  * same draws as for +-1 couplings, where expd is exp evaluated as 2^k e^r, k = floor(x / ln 2 +
  * 1/2), r = (x - k ln2_hi) - k ln2_lo (ln2_hi = 0.6931471803691238, ln2_lo =
  * 1.9082149292705877e-10), e^r by its Taylor series to r^13 in Horner form, and 0 below -745.
- * Resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))), S = sum over consecutive blocks
- * of 256 replicas (in order) of the blocks' sums (in order), ln Q = -dbeta E_lo + ln S - ln R~,
+ * Resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))), S = sum of w_j added in replica
+ * order j = 0, 1, ... (eq. Q), ln Q = -dbeta E_lo + ln S - ln R~,
  * copies of j ~ Poisson((R_target w_j) / S) by the ladder of pa_resample.  FP64 products and
  * sums are never fused.  In calls with n_runs > 1, Gaussian runs whose pa_state blocks are
  * consecutive and share a stream take one launch per kernel, others one after the other;
@@ -243,7 +243,7 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step);
  *   of replica j at offsets[j] .. offsets[j] + copies - 1 (source order).
  * Writes record[k].beta .. E_lo.  Raises PA_FLAG_CAPACITY (R~' > capacity),
  * PA_FLAG_EXTINCT (R~' = 0) or PA_FLAG_NONFINITE, in which case the population, the
- * accumulator and k are left unchanged.  step->weights must hold n_bins entries for
+ * accumulator, k and record[k] are left unchanged.  step->weights must hold n_bins entries for
  * dbeta = beta_to - beta_from (pa_fill_weights). */
 int pa_resample(pa_run* runs, int n_runs, const pa_step* step);
 
@@ -274,6 +274,19 @@ int pa_weighted_average(int M, const double* minus_betaF, const double* R, const
  * A_bar[0..n_obs-1], -beta F_bar, var, mean.  All pointers are device pointers. */
 int pa_weighted_average_dev(int n_sets, int M, const double* minus_betaF, const double* R, const double* A,
                             int n_obs, double* out, void* stream);
+
+/* Overlap observables of pairs of runs on the device (Sec. IV, eqs. pqs and omegaprime), for n_sets
+ * independent sets of n_pairs pairs.  Pair p of set s joins runs 2p and 2p + 1 of that set:
+ * minus_betaF[s][2 n_pairs] holds -beta F~ of every run and R[s][2 n_pairs] its target size (NULL:
+ * equal sizes); Q[s][n_pairs][3] holds the pair's <q^2>, <q^4> and Gamma (record[k].q2, q4, gamma
+ * of a pa_measure call with that partner).  The pair weight is
+ *   omega'_p = R^(1) R^(2) exp(x^(1) + x^(2)) / sum over pairs of the same,  x = minus_betaF,
+ * and out[s][4] receives the weighted [q^2], [q^4], [Gamma] and the Binder ratio
+ *   g = (3 - [q^4] / [q^2]^2) / 2.
+ * All pointers are device pointers; asynchronous on stream.  PA_ERR_ARG for n_sets or n_pairs
+ * not positive or a NULL array other than R. */
+int pa_overlap_average_dev(int n_sets, int n_pairs, const double* minus_betaF, const double* R, const double* Q,
+                           double* out, void* stream);
 
 /* Bootstrap errors of the device weighted averages (Sec. III: the error is the standard
  * deviation over resampled ensembles, each of M runs).  idx is device int32 [n_boot][M]: run

@@ -72,6 +72,7 @@ def lib():
         L.orc_overlap_hist.restype = i64
         L.orc_overlap_stats.argtypes = [i32, P, P]
         L.orc_weighted_average.argtypes = [i32, P, P, P, i32, P, P, P, P, P]
+        L.orc_overlap_average.argtypes = [i32, P, P, P, P]
         L.orc_run.argtypes = [i32, i32, P, u64, i64, i32, P, P, i32, i64, P, P, P, P]
         L.orc_num_threads.argtypes = []
         L.orc_expd.argtypes = [f64]
@@ -240,6 +241,22 @@ def weighted_average(x, A=None, R=None):
                                     ctypes.byref(mbF), ctypes.byref(var), ctypes.byref(mean))
     assert st == OK
     return dict(A_bar=A_bar[:n_obs], omega=omega, minus_betaF_bar=mbF.value, var=var.value, mean=mean.value)
+
+
+def overlap_average(x, Q, R=None):
+    """Weighted overlap observables over pairs of runs (Sec. IV, eqs. pqs and omegaprime).
+    x: [2 n_pairs] of -beta F~ per run (pair p = runs 2p, 2p + 1); Q: [n_pairs][3] of the pair's
+    (<q^2>, <q^4>, Gamma); R: [2 n_pairs] target sizes or None.  Returns ([q^2], [q^4], [Gamma], g)
+    with the Binder ratio g = (3 - [q^4] / [q^2]^2) / 2."""
+    x = np.ascontiguousarray(x, np.float64)
+    Q = np.ascontiguousarray(np.asarray(Q, np.float64).reshape(-1, 3))
+    n = Q.shape[0]
+    assert len(x) == 2 * n
+    Rr = None if R is None else np.ascontiguousarray(R, np.float64)
+    out = np.zeros(4)
+    st = lib().orc_overlap_average(n, _p(x), _p(Rr), _p(Q), _p(out))
+    assert st == OK
+    return out
 
 
 def run(dim, L, J, seed, R0, betas, ns, capacity=None, R_targets=None):

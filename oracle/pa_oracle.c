@@ -561,6 +561,36 @@ int orc_weighted_average(int M, const double* x, const double* Rr, const double*
 }
 
 /* ------------------------------------------------------------------------- */
+/* Overlap observables over pairs of independent runs (Sec. IV, eqs. pqs and    */
+/* omegaprime): pair p is runs 2p and 2p+1; its weight is proportional to       */
+/* exp(-beta (F~^(1) + F~^(2))), times R^(1) R^(2) for runs with unequal target */
+/* sizes (Sec. III).  Q is [n_pairs][3]: the pair's <q^2>, <q^4> and Gamma.     */
+/* out = ([q^2], [q^4], [Gamma], g) with the Binder ratio                       */
+/*   g = (3 - [q^4] / [q^2]^2) / 2                                              */
+/* of the weighted moments (not a paper quantity: the observable the 3D         */
+/* configuration asks for).                                                    */
+/* ------------------------------------------------------------------------- */
+int orc_overlap_average(int n_pairs, const double* x, const double* Rr, const double* Q, double* out)
+{
+    if (n_pairs <= 0) return ORC_ERR_ARG;
+    double* xp = (double*)malloc((size_t)n_pairs * sizeof(double));
+    double* Rp = Rr ? (double*)malloc((size_t)n_pairs * sizeof(double)) : NULL;
+    double* omega = (double*)malloc((size_t)n_pairs * sizeof(double));
+    for (int p = 0; p < n_pairs; ++p) {
+        xp[p] = x[2 * p] + x[2 * p + 1];
+        if (Rr) Rp[p] = Rr[2 * p] * Rr[2 * p + 1];
+    }
+    double mbF, var, mean;
+    int st = orc_weighted_average(n_pairs, xp, Rp, Q, 3, out, omega, &mbF, &var, &mean);
+    free(xp);
+    free(Rp);
+    free(omega);
+    if (st != ORC_OK) return st;
+    out[3] = 0.5 * (3.0 - out[1] / (out[0] * out[0]));
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* A whole run, in the order of the paper's algorithm: initialise R0 replicas  */
 /* at beta_0 = 0; for each later temperature: resample (Q, tau, Poisson copies) */
 /* then theta sweeps, then measure and record -beta F~ = ln Omega + sum ln Q    */
@@ -641,8 +671,8 @@ int orc_run(int dim, int L, const int8_t* J, uint64_t seed, int64_t R0, int nT, 
 /*   accept dE <= 0; otherwise p = expd(-(beta dE)); accept if p >= 1, else    */
 /*        with T64 = (uint64) (p 2^64) by the lazy 16 + 48-bit compare;        */
 /*   resampling: E_lo = min E, w_j = expd(-(dbeta (E_j - E_lo))),              */
-/*        S = sum over blocks of 256 consecutive replicas (in order) of the     */
-/*        block's sum (in order), ln Q = -dbeta E_lo + ln S - ln R~,           */
+/*        S = sum of w_j over j = 0, 1, ... in replica order (eq. Q),         */
+/*        ln Q = -dbeta E_lo + ln S - ln R~,                                   */
 /*        copies of j ~ Poisson((R_target w_j) / S) as for +-J couplings.      */
 /* expd is exp written out: x = k ln 2 + r with k = floor(x / ln 2 + 1/2), r   */
 /* by a two-part ln 2 (Cody and Waite), e^r by its Taylor series to r^13 in    */
@@ -758,12 +788,9 @@ int orc_copy_numbers_gauss(uint64_t seed, int64_t k, double beta_from, double be
     double E_lo = E[0];
     for (int64_t j = 1; j < R; ++j)
         if (E[j] < E_lo) E_lo = E[j];
+    /* eq. Q with the energies shifted by E_lo, summed over the replicas in their order */
     double S = 0.0;
-    for (int64_t b0 = 0; b0 < R; b0 += 256) {
-        double part = 0.0;
-        for (int64_t j = b0; j < R && j < b0 + 256; ++j) part = part + orc_expd(-(dbeta * (E[j] - E_lo)));
-        S = S + part;
-    }
+    for (int64_t j = 0; j < R; ++j) S = S + orc_expd(-(dbeta * (E[j] - E_lo)));
     out[0] = S;
     out[1] = -dbeta * E_lo + log(S) - log((double)R);
     out[2] = E_lo;

@@ -336,6 +336,13 @@ int pa_weighted_average_dev(int n_sets, int M, const double* x, const double* R,
     return launch_weighted_average_dev(n_sets, M, x, R, A, n_obs, out, (hipStream_t)stream);
 }
 
+int pa_overlap_average_dev(int n_sets, int n_pairs, const double* minus_betaF, const double* R, const double* Q,
+                           double* out, void* stream)
+{
+    if (n_sets <= 0 || n_pairs <= 0 || !minus_betaF || !Q || !out) return PA_ERR_ARG;
+    return launch_overlap_average_dev(n_sets, n_pairs, minus_betaF, R, Q, out, (hipStream_t)stream);
+}
+
 int pa_bootstrap_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs, int n_boot,
                      const int32_t* idx, double* rep, double* err, void* stream)
 {

@@ -121,6 +121,8 @@ bool fast_sweep_supported(int dim, int L);
 int build_sweep_params(const pa_step& step, int z, SweepParams* p);
 int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
                                 double* out, hipStream_t s);
+int launch_overlap_average_dev(int n_sets, int n_pairs, const double* x, const double* R, const double* Q,
+                               double* out, hipStream_t s);
 int launch_bootstrap_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs, int n_boot,
                          const int32_t* idx, double* rep, double* err, hipStream_t s);
 int build_thresholds(double beta, int z, uint64_t* T, uint8_t* always);

@@ -300,6 +300,47 @@ int launch_weighted_average_dev(int n_sets, int M, const double* x, const double
     return hip_status(hipGetLastError());
 }
 
+// Overlap observables over pairs of runs (Sec. IV, eqs. pqs and omegaprime), one thread per set:
+// pair p joins runs 2p and 2p + 1 and weighs exp(x^(1) + x^(2)) (times R^(1) R^(2) when R is
+// given, Sec. III); Q holds each pair's (<q^2>, <q^4>, Gamma).  The weighted moments give the
+// Binder ratio g = (3 - [q^4] / [q^2]^2) / 2.  o = ([q^2], [q^4], [Gamma], g).
+__global__ void k_overlap_average(int n_sets, int n_pairs, const double* __restrict__ x, const double* __restrict__ R,
+                                  const double* __restrict__ Q, double* __restrict__ out)
+{
+    const int set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets) return;
+    const double* xs = x + (int64_t)set * 2 * n_pairs;
+    const double* Rs = R ? R + (int64_t)set * 2 * n_pairs : nullptr;
+    const double* Qs = Q + (int64_t)set * n_pairs * 3;
+    // exponent of pair p: x^(1) + x^(2) (+ ln(R^(1) R^(2)))
+    auto xpair = [&](int p) {
+        const double xp = xs[2 * p] + xs[2 * p + 1];
+        return xp + (Rs ? log(Rs[2 * p] * Rs[2 * p + 1]) : 0.0);
+    };
+    double xmax = -INFINITY;
+    for (int p = 0; p < n_pairs; ++p) xmax = fmax(xmax, xpair(p));
+    double Z = 0.0;
+    for (int p = 0; p < n_pairs; ++p) Z += exp(xpair(p) - xmax);
+    double o[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < n_pairs; ++p) {
+        const double w = exp(xpair(p) - xmax) / Z;
+        for (int k = 0; k < 3; ++k) o[k] += w * Qs[3 * p + k];
+    }
+    double* os = out + (int64_t)set * 4;
+    os[0] = o[0];
+    os[1] = o[1];
+    os[2] = o[2];
+    os[3] = 0.5 * (3.0 - o[1] / (o[0] * o[0]));
+}
+
+int launch_overlap_average_dev(int n_sets, int n_pairs, const double* x, const double* R, const double* Q,
+                               double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_overlap_average, dim3((unsigned)((n_sets + 63) / 64)), dim3(64), 0, s, n_sets, n_pairs, x, R,
+                       Q, out);
+    return hip_status(hipGetLastError());
+}
+
 // bootstrap replicates: thread per (set, replicate b), the weighted average of the runs idx[b][.]
 __global__ void k_bootstrap(int n_sets, int M, const double* __restrict__ x, const double* __restrict__ R,
                             const double* __restrict__ A, int n_obs, int n_boot, const int32_t* __restrict__ idx,

@@ -27,7 +27,10 @@ namespace pa {
 // Poisson(2^m) inversion tables, m = kLadderMin .. kLadderMax (host-built, uploaded once)
 __device__ uint64_t g_ladder[kLadderLevels][kLadderCap];
 
-constexpr int kMiscEmin = 0, kMiscEmax = 1, kMiscLnQ = 2;  // int64 slots of the misc area
+// int64 slots of the misc area: E_lo and E_hi of the population being resampled (FP64 bits of E_lo
+// with Gaussian couplings), then ln Q and S of the step (FP64 bits), kept there until k_finish
+// commits the step to the run's state and record
+constexpr int kMiscEmin = 0, kMiscEmax = 1, kMiscLnQ = 2, kMiscS = 3;
 
 // ------------------------------------------------------------------ host tables
 // C[n] = floor(CDF_{2^m}(n) 2^32) with pmf recursion p_0 = exp(-Lambda), p_n = p_{n-1} Lambda / n;
@@ -95,8 +98,10 @@ __global__ void k_hist_clear(pa_state* base)
     }
 }
 
-// histogram of the current population's energies (LDS-privatised when it fits)
-__global__ void __launch_bounds__(256) k_hist(pa_state* base)
+// histogram of the current population's energies, counted in an LDS copy of cap_bins entries
+// when the run's bins fit there (the LDS is sized for the call, whose runs may differ in size),
+// else directly in global memory
+__global__ void __launch_bounds__(256) k_hist(pa_state* base, int cap_bins)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(256) k_hist(pa_state* base)
     int64_t* hist = work_ptr<int64_t>(st, wl.hist);
     int64_t* misc = work_ptr<int64_t>(st, wl.misc);
     const int nb = st->n_bins;
-    const bool priv = nb <= 16384;
+    const bool priv = nb <= cap_bins;
     const int64_t R = st->R;
     const int32_t* E = st->energy[st->cur];
     const int Eb = st->E_base;
@@ -150,7 +155,8 @@ __device__ inline int ladder_level(double x)
     return m < kLadderMin ? kLadderMin : m;
 }
 
-// one block: S in ascending energy order, ln Q, per-bin Poisson parameters, record[k]
+// one block: S in ascending energy order, ln Q, per-bin Poisson parameters (the step's record is
+// written by k_finish, once the new population is known to fit)
 __global__ void __launch_bounds__(256) k_normalise(pa_state* base, ResampleParams p)
 {
     pa_state* st = base + blockIdx.y;
@@ -188,13 +194,8 @@ __global__ void __launch_bounds__(256) k_normalise(pa_state* base, ResampleParam
         if (bad) {
             st->status |= PA_FLAG_NONFINITE;
         } else {
-            pa_record* rec = st->record + p.k;
-            rec->beta = p.beta_to;
-            rec->lnQ = lnQ;
-            rec->minus_betaF = st->ln_omega + (st->acc + lnQ);
-            rec->S = S;
-            rec->E_lo = (double)E_lo;
             *reinterpret_cast<double*>(&misc[kMiscLnQ]) = lnQ;
+            *reinterpret_cast<double*>(&misc[kMiscS]) = S;
             st->E_lo = E_lo;
             st->E_hi = E_hi;
         }
@@ -436,6 +437,8 @@ __global__ void __launch_bounds__(256) k_gather_bits(pa_state* base)
     st->energy[st->cur ^ 1][rn] = st->energy[st->cur][j];
 }
 
+// commit an accepted step: swap the buffers, accumulate ln Q (eq. sumQ) and write record[k]; a step
+// refused by a sticky flag leaves state and records as they were
 __global__ void k_finish(pa_state* base, ResampleParams p)
 {
     pa_state* st = base + blockIdx.y;
@@ -443,12 +446,20 @@ __global__ void k_finish(pa_state* base, ResampleParams p)
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
     const double lnQ = *reinterpret_cast<const double*>(&misc[kMiscLnQ]);
+    const double E_lo = st->couplings == PA_GAUSS ? *reinterpret_cast<const double*>(&misc[kMiscEmin])
+                                                  : (double)misc[kMiscEmin];
+    pa_record* rec = st->record + p.k;
+    rec->beta = p.beta_to;
+    rec->lnQ = lnQ;
+    rec->minus_betaF = st->ln_omega + (st->acc + lnQ);
+    rec->S = *reinterpret_cast<const double*>(&misc[kMiscS]);
+    rec->R = (double)st->R_new;
+    rec->E_lo = E_lo;
     st->acc = st->acc + lnQ;
     st->cur ^= 1;
     st->R = st->R_new;
     st->k = p.k;
     st->beta = p.beta_to;
-    st->record[p.k].R = (double)st->R_new;
 }
 
 // Launch shapes cover the largest run of the call; grid.y indexes the runs, whose states
@@ -473,13 +484,21 @@ static BatchShape batch_shape(const pa_run* runs, int n)
 int launch_hist(const pa_run* runs, int n, hipStream_t s)
 {
     const BatchShape b = batch_shape(runs, n);
-    const size_t hist_lds = b.bins_max <= 16384 ? (size_t)b.bins_max * 4 : 0;
+    // an LDS histogram of up to 16384 bins, sized for the largest run of the call that fits (runs
+    // with more bins count in global memory)
+    int64_t cap_bins = 0;
+    for (int r = 0; r < n; ++r) {
+        pa_sizes sz;
+        pa_buffer_sizes(runs[r].dim, runs[r].L, runs[r].layout, runs[r].couplings, runs[r].capacity, runs[r].n_records, &sz);
+        if (sz.n_bins <= 16384) cap_bins = std::max(cap_bins, sz.n_bins);
+    }
+    const size_t hist_lds = (size_t)cap_bins * 4;
     // few blocks: each block zeroes and scans all bins of its LDS histogram and merges the occupied
     // ones with global atomics that land on the same few bins (L = 16, 1e6 replicas: 1024 blocks
     // 98 us, 256 blocks 29 us, 128 blocks 21 us)
     const unsigned hist_blocks = (unsigned)std::min<int64_t>(128, (b.cap_max + 255) / 256);
     hipLaunchKernelGGL(k_hist_clear, dim3(32, n), dim3(256), 0, s, runs[0].state);
-    hipLaunchKernelGGL(k_hist, dim3(hist_blocks, n), dim3(256), hist_lds, s, runs[0].state);
+    hipLaunchKernelGGL(k_hist, dim3(hist_blocks, n), dim3(256), hist_lds, s, runs[0].state, (int)cap_bins);
     return PA_OK;
 }
 
@@ -514,11 +533,11 @@ int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t 
 
 // ------------------------------------------------------------------ Gaussian couplings
 // Real energies: per-replica weights instead of the energy histogram.  E_lo = min E (exact);
-// w_j = expd(-(dbeta (E_j - E_lo))); S = sum over blocks of 256 consecutive replicas of their
-// in-order sums, added in block order; ln Q = -dbeta E_lo + ln S - ln R~; copies of j ~
-// Poisson((R_target w_j) / S) by the same ladder and draws as the histogram path.
-constexpr int kMiscGaussS = 3;      // misc slot: S (FP64 bits)
-constexpr int kGaussBlock = 256;
+// w_j = expd(-(dbeta (E_j - E_lo))); S = sum of w_j over j = 0, 1, ... in replica order (eq. Q);
+// ln Q = -dbeta E_lo + ln S - ln R~; copies of j ~ Poisson((R_target w_j) / S) by the same ladder
+// and draws as the histogram path.  The weights are kept in the inactive energy buffer (FP64,
+// [capacity]) between their evaluation and the copy numbers; the gather overwrites them.
+constexpr int kMiscGaussS = kMiscS;  // misc slot: S (FP64 bits)
 
 __global__ void __launch_bounds__(256) k_gauss_min(pa_state* base)
 {
@@ -540,49 +559,46 @@ __global__ void __launch_bounds__(256) k_gauss_min(pa_state* base)
     }
 }
 
-// thread per block of 256 replicas: its in-order weight sum, kept in the source-index area
-__global__ void __launch_bounds__(256) k_gauss_blocksum(pa_state* base, double dbeta)
+// thread per replica: its weight w_j into the inactive energy buffer
+__global__ void __launch_bounds__(256) k_gauss_weights(pa_state* base, double dbeta)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t R = st->R;
-    if (b * kGaussBlock >= R) return;
-    const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
-    const int64_t* misc = work_ptr<int64_t>(st, wl.misc);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= st->R) return;
+    const int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
     const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
     const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
-    double part = 0.0;
-    const int64_t j1 = min(R, (b + 1) * kGaussBlock);
-    for (int64_t j = b * kGaussBlock; j < j1; ++j) part = part + expd(-(dbeta * (E[j] - E_lo)));
-    work_ptr<double>(st, wl.src)[b] = part;
+    double* w = reinterpret_cast<double*>(st->energy[st->cur ^ 1]);
+    w[j] = expd(-(dbeta * (E[j] - E_lo)));
 }
 
+// one thread per run: S in replica order, ln Q (the step's record is written by k_finish)
 __global__ void k_gauss_normalise(pa_state* base, ResampleParams p)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     int64_t* misc = work_ptr<int64_t>(st, wl.misc);
-    const double* part = work_ptr<double>(st, wl.src);
+    const double* w = reinterpret_cast<const double*>(st->energy[st->cur ^ 1]);
     const int64_t R = st->R;
-    const int64_t nb = (R + kGaussBlock - 1) / kGaussBlock;
     double S = 0.0;
-    for (int64_t b = 0; b < nb; ++b) S = S + part[b];
+    int64_t j = 0;
+    for (; j + 8 <= R; j += 8) {  // the loads ahead of the (ordered) additions
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = w[j + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S = S + v[u];
+    }
+    for (; j < R; ++j) S = S + w[j];
     const double dbeta = p.beta_to - p.beta_from;
     const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
     if (!isfinite(S) || !(S > 0.0)) {
         st->status |= PA_FLAG_NONFINITE;
         return;
     }
-    const double lnQ = -dbeta * E_lo + log(S) - log((double)R);
-    pa_record* rec = st->record + p.k;
-    rec->beta = p.beta_to;
-    rec->lnQ = lnQ;
-    rec->minus_betaF = st->ln_omega + (st->acc + lnQ);
-    rec->S = S;
-    rec->E_lo = E_lo;
-    *reinterpret_cast<double*>(&misc[kMiscLnQ]) = lnQ;
+    *reinterpret_cast<double*>(&misc[kMiscLnQ]) = -dbeta * E_lo + log(S) - log((double)R);
     *reinterpret_cast<double*>(&misc[kMiscGaussS]) = S;
 }
 
@@ -593,12 +609,10 @@ __global__ void __launch_bounds__(256) k_gauss_copies(pa_state* base, ResamplePa
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= st->R) return;
     const int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
-    const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
     const double S = *reinterpret_cast<const double*>(&misc[kMiscGaussS]);
-    const double* E = reinterpret_cast<const double*>(st->energy[st->cur]);
-    const double dbeta = p.beta_to - p.beta_from;
+    const double* w = reinterpret_cast<const double*>(st->energy[st->cur ^ 1]);
     const double Rt = p.R_target > 0.0 ? p.R_target : (double)st->R0;
-    const double lam = (Rt * expd(-(dbeta * (E[j] - E_lo)))) / S;
+    const double lam = (Rt * w[j]) / S;
     int64_t n = 0;
     if (lam > 0.0) {
         int64_t q = 0;
@@ -644,11 +658,9 @@ int launch_resample_gauss(const pa_run* runs, int n, const pa_step& step, hipStr
     }
     const unsigned cap_blocks = (unsigned)((cap + 255) / 256);
     const unsigned n_scan = (unsigned)((cap + kScanTile - 1) / kScanTile);
-    const int64_t n_part = (cap + kGaussBlock - 1) / kGaussBlock;
     const unsigned ny = (unsigned)n;
     hipLaunchKernelGGL(k_gauss_min, dim3(1, ny), dim3(256), 0, s, base);
-    hipLaunchKernelGGL(k_gauss_blocksum, dim3((unsigned)((n_part + 255) / 256), ny), dim3(256), 0, s, base,
-                       step.beta_to - step.beta_from);
+    hipLaunchKernelGGL(k_gauss_weights, dim3(cap_blocks, ny), dim3(256), 0, s, base, step.beta_to - step.beta_from);
     hipLaunchKernelGGL(k_gauss_normalise, dim3(1, ny), dim3(1), 0, s, base, p);
     hipLaunchKernelGGL(k_gauss_copies, dim3(cap_blocks, ny), dim3(256), 0, s, base, p);
     hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, ny), dim3(256), 0, s, base);

@@ -5,7 +5,7 @@ sweep, the whole schedule captured as one HIP graph), then per realisation the r
 R^(r) exp(-beta F~_r) (runs with unequal target sizes, Sec. III) give the weighted energy
 and free energy, and the pair weights R^(1) R^(2) exp(-beta (F~^(1) + F~^(2))) of the overlap
 pairs give the weighted <q^2>, <q^4>, Gamma and the Binder ratio, computed on the device by
-pa_weighted_average_dev.
+pa_weighted_average_dev and pa_overlap_average_dev.
 """
 from __future__ import annotations
 
@@ -31,28 +31,24 @@ def weighted_by_realization(records, specs, k, device="cuda"):
     x = records[idx, k, REC["minus_betaF"]]
     R = np.array([[specs[i]["R0"] for i in row] for row in idx], dtype=np.float64)
     E = records[idx, k, REC["E_mean"]][..., None]
-    # overlap pairs (0,1), (2,3), ...: x and R of a pair are sums and products
-    xp = x[:, 0::2] + x[:, 1::2]
-    Rp = R[:, 0::2] * R[:, 1::2]
+    # overlap pairs (0,1), (2,3), ...: the overlap observables sit in the first run of each pair
     Q = np.stack([records[idx[:, 0::2], k, REC["q2"]], records[idx[:, 0::2], k, REC["q4"]],
                   records[idx[:, 0::2], k, REC["gamma"]]], axis=-1)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)  # noqa: E731
     n_real = len(reals)
     out_e = torch.zeros((n_real, 1 + 3), dtype=torch.float64, device=device)
-    out_q = torch.zeros((n_real, 3 + 3), dtype=torch.float64, device=device)
+    out_q = torch.zeros((n_real, 4), dtype=torch.float64, device=device)
     s = torch.cuda.current_stream(device).cuda_stream
-    xd, Rd, Ed = dev(x), dev(R), dev(E)
-    xpd, Rpd, Qd = dev(xp), dev(Rp), dev(Q)
+    xd, Rd, Ed, Qd = dev(x), dev(R), dev(E), dev(Q)
     pa.check(pa.lib().pa_weighted_average_dev(n_real, M, xd.data_ptr(), Rd.data_ptr(), Ed.data_ptr(), 1,
                                               out_e.data_ptr(), s), "pa_weighted_average_dev")
-    pa.check(pa.lib().pa_weighted_average_dev(n_real, M // 2, xpd.data_ptr(), Rpd.data_ptr(), Qd.data_ptr(), 3,
-                                              out_q.data_ptr(), s), "pa_weighted_average_dev")
+    pa.check(pa.lib().pa_overlap_average_dev(n_real, M // 2, xd.data_ptr(), Rd.data_ptr(), Qd.data_ptr(),
+                                             out_q.data_ptr(), s), "pa_overlap_average_dev")
     oe = out_e.cpu().numpy()
     oq = out_q.cpu().numpy()
-    q2, q4 = oq[:, 0], oq[:, 1]
     return dict(realizations=reals, E_bar=oe[:, 0], minus_betaF_bar=oe[:, 1], var_betaF=oe[:, 2],
-                mean_minus_betaF=oe[:, 3], q2=q2, q4=q4, gamma=oq[:, 2],
-                binder=0.5 * (3.0 - q4 / (q2 * q2)), L=np.array([specs[i[0]]["L"] for i in idx]))
+                mean_minus_betaF=oe[:, 3], q2=oq[:, 0], q4=oq[:, 1], gamma=oq[:, 2], binder=oq[:, 3],
+                L=np.array([specs[i[0]]["L"] for i in idx]))
 
 
 def run_batched(specs, n_temps, n_sweeps, layout="bits64", device="cuda", tune=True, graph=True, verbose=False):

@@ -99,6 +99,7 @@ SIGNATURES = {
     "pa_mlp_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, P]),
     "pa_bf16_round": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
+    "pa_overlap_average_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
     "pa_bootstrap_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P, P]),
 }
 

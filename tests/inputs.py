@@ -56,3 +56,16 @@ def float32_values(seed, n):
     special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-40, -1e-40, 3.4e38, -3.4e38], np.float32)
     x[-len(special):] = special
     return x
+
+
+def overlap_pair_sets(seed, n_sets, n_pairs):
+    """Inputs of a pair-weighted overlap average: -beta F~ per run [n_sets][2 n_pairs] (spread over
+    a few units around 900, so the weights differ widely), target sizes [n_sets][2 n_pairs] and
+    per-pair (<q^2>, <q^4>, Gamma) [n_sets][n_pairs][3] with <q^2>^2 <= <q^4> <= <q^2>."""
+    g = np.random.default_rng(seed)
+    x = 900.0 + 3.0 * g.standard_normal((n_sets, 2 * n_pairs))
+    R = g.uniform(1e4, 1e5, (n_sets, 2 * n_pairs))
+    q2 = g.uniform(0.05, 0.9, (n_sets, n_pairs))
+    q4 = q2 * q2 + g.uniform(0.0, 1.0, (n_sets, n_pairs)) * (q2 - q2 * q2)
+    gam = g.uniform(0.0, 0.3, (n_sets, n_pairs))
+    return x, R, np.stack([q2, q4, gam], axis=-1)

@@ -97,6 +97,43 @@ def test_batch_matches_oracle():
         assert np.allclose(rec[:, 2], rec_o[:, 3], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("specs,ns", [
+    ([dict(dim=3, L=8, R0=300, seed=41, disorder_seed=2), dict(dim=3, L=24, R0=150, seed=42, disorder_seed=3)], 2),
+    ([dict(dim=1, L=64, R0=400, seed=43, disorder_seed=4), dict(dim=1, L=40000, R0=120, seed=44, disorder_seed=5)], 0),
+], ids=["cube_8_24", "chain_64_40000"])
+def test_batch_histogram_of_runs_with_and_without_lds_bins(specs, ns):
+    # the histogram kernel counts a run's energies in LDS when its bins fit the call's LDS table and
+    # in global memory otherwise: a batch that mixes both (the larger lattice has more than 16384
+    # bins) must equal the runs stepped one by one, and the oracle's first resampling (the chain
+    # steps without sweeps: a 40000-site chain row does not fit the sweep's LDS)
+    nT = 4
+    betas = [0.0, 0.3, 0.9, 1.6]
+    note(f"mixed histogram batch L={[sp['L'] for sp in specs]}")
+    batch = pa.Batch(specs, nT, layout="bits64", device=DEV).init()
+    solos = solo_runs(specs, nT, "bits64", [r.capacity for r in batch.runs])
+    sched = pa.Schedule(betas, ns, max(r.n_bins for r in batch.runs), device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k)
+        st = sched.step(k)
+        for r in solos:
+            r.resample(st)
+            r.sweep(st)
+        pa.measure(solos)
+        compare(batch, solos, k)
+        if k == 1:
+            for sp, run in zip(specs, batch.runs):
+                J = o.couplings(sp["dim"], sp["L"], sp["disorder_seed"])
+                _, E0 = o.init_population(sp["dim"], sp["L"], J, sp["seed"], sp["R0"])
+                stc, counts_o, S_o, _, Elo_o = o.copy_numbers(sp["seed"], 1, betas[0], betas[1], sp["R0"], E0)
+                assert stc == 0
+                c, _ = run.counts_offsets(sp["R0"])
+                assert np.array_equal(c, counts_o)
+                rec = run.records()[1]
+                assert rec[3] == S_o and rec[5] == Elo_o
+    code, flags = batch.status()
+    assert code == pa.PA_OK and not flags.any()
+
+
 def test_graph_replays_equal_eager():
     specs = specs_mixed()[:8]
     nT, ns = 6, 2
@@ -195,9 +232,13 @@ def test_ensemble_weighted_averages_and_autotuner():
         assert abs(w["var_betaF"][n] - ref["var"]) <= 1e-12 * max(1.0, ref["var"])
         xp = x[0::2] + x[1::2]
         Rp = R[0::2] * R[1::2]
-        q2 = rec[np.array(idx)[0::2], k, 9]
-        refq = pa.weighted_average(xp, q2[:, None], Rp)
-        assert abs(w["q2"][n] - refq["A_bar"][0]) <= 1e-12
+        Q = rec[np.array(idx)[0::2], k, 9:12]
+        q2 = Q[:, 0]
+        refq = pa.weighted_average(xp, Q, Rp)
+        for v, name in enumerate(("q2", "q4", "gamma")):
+            assert abs(w[name][n] - refq["A_bar"][v]) <= 1e-12, name
+        g = 0.5 * (3.0 - refq["A_bar"][1] / refq["A_bar"][0] ** 2)
+        assert abs(w["binder"][n] - g) <= 1e-12 * max(1.0, abs(g))
         assert E.min() - 1e-9 <= w["E_bar"][n] <= E.max() + 1e-9 and w["var_betaF"][n] >= 0.0
         assert q2.min() - 1e-12 <= w["q2"][n] <= q2.max() + 1e-12
     from paper_1006_0252_amd import autotune

@@ -247,6 +247,7 @@ def test_capacity_and_extinction_flags_leave_state_unchanged():
     note("capacity overflow")
     run = make_run(dim, L, R0, "bits64", capacity=256)
     s0, E0 = run.population()
+    rec0 = run.records()
     sched = pa.Schedule([0.0, 0.1], 1, run.n_bins, device=DEV, R_targets=[0, 5000.0])
     run.resample(sched.step(1))
     code, flags = run.status()
@@ -255,6 +256,7 @@ def test_capacity_and_extinction_flags_leave_state_unchanged():
     assert info.R == R0 and info.k == 0 and info.R_new > 256
     s1, E1 = run.population()
     assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
+    assert np.array_equal(run.records(), rec0), "a refused step must not write its record"
     # sticky: later calls do nothing
     run.sweep(sched.step(1))
     s2, _ = run.population()
@@ -262,10 +264,12 @@ def test_capacity_and_extinction_flags_leave_state_unchanged():
     note("extinction")
     run = make_run(dim, L, R0, "u8")
     sched = pa.Schedule([0.0, 0.1], 1, run.n_bins, device=DEV, R_targets=[0, 1e-9])
+    rec0 = run.records()
     run.resample(sched.step(1))
     code, flags = run.status()
     assert code == pa.PA_ERR_EXTINCT and flags & pa.PA_FLAG_EXTINCT
     assert run.query().R == R0
+    assert np.array_equal(run.records(), rec0)
 
 
 def test_bad_step_rejected_on_host():
@@ -306,6 +310,27 @@ def test_device_weighted_average_matches_host():
         assert close(res[s_, n_obs + 1], ref["var"]) and close(res[s_, n_obs + 2], ref["mean"])
 
 
+def test_device_overlap_average_matches_oracle():
+    # pair-weighted overlap observables and the Binder ratio (Sec. IV, eqs. pqs and omegaprime) on
+    # seeded inputs, with and without target sizes, against the oracle
+    from tests import inputs
+
+    for n_sets, n_pairs, use_R in ((3, 50, True), (5, 1, False), (1, 7, False)):
+        note(f"device overlap average sets={n_sets} pairs={n_pairs} R={use_R}")
+        x, R, Q = inputs.overlap_pair_sets(17 + n_pairs, n_sets, n_pairs)
+        out = torch.zeros((n_sets, 4), dtype=torch.float64, device=DEV)
+        xd, Rd, Qd = (torch.tensor(a, device=DEV) for a in (x, R, Q))
+        pa.check(pa.lib().pa_overlap_average_dev(n_sets, n_pairs, xd.data_ptr(), Rd.data_ptr() if use_R else None,
+                                                 Qd.data_ptr(), out.data_ptr(),
+                                                 torch.cuda.current_stream().cuda_stream))
+        res = out.cpu().numpy()
+        for s_ in range(n_sets):
+            ref = o.overlap_average(x[s_], Q[s_], R[s_] if use_R else None)
+            for v in range(4):
+                assert close(res[s_, v], ref[v]), f"set {s_} value {v}: {res[s_, v]} vs {ref[v]}"
+    assert pa.lib().pa_overlap_average_dev(1, 0, xd.data_ptr(), None, Qd.data_ptr(), out.data_ptr(), None) == pa.PA_ERR_ARG
+
+
 def test_full_size_c4_sampled():
     # the throughput configuration at its real size: L = 16, R0 = 1e6, bit-packed.  The oracle sweeps
     # sampled replicas one by one from its own initial spins (a replica's sweep depends only on its
@@ -325,19 +350,23 @@ def test_full_size_c4_sampled():
     init_o = [o.init_replicas(dim, L, J, seed, int(r), 1) for r in sample]
     for n, r in enumerate(sample):
         assert np.array_equal(s[n], init_o[n][0][0]) and E[r] == init_o[n][1][0]
-    note("C4 full size: sweep beta=1.0")
-    betas = [0.0, 1.0, 1.0 + 1.0 / 60.0]
+    # ten sweeps at beta = 1, 2 and 4 in turn: the three first-look regimes of the sweep kernel
+    # (general thresholds; only dE = 4 with a non-zero top; all tops zero)
+    betas = [0.0, 4.0, 4.0 + 1.0 / 60.0]
     sched = pa.Schedule(betas, 10, run.n_bins, device=DEV)
-    st = sched.step(1)
-    st.t0 = 120
-    run.sweep(st)
-    s1 = run.replica_spins(sample)
-    E1 = run.energies()
-    for n, r in enumerate(sample):
-        so, Eo = init_o[n]
-        o.sweep_replicas(dim, L, J, seed, 1.0, int(r), so, Eo, 120, 10)
-        assert np.array_equal(s1[n], so[0]) and E1[r] == Eo[0], f"replica {r}"
-    note("C4 full size: resample 1.0 -> 1.0 + 1/60")
+    for t0, beta in ((120, 1.0), (130, 2.0), (140, 4.0)):
+        note(f"C4 full size: sweep beta={beta}")
+        st = sched.step(1)
+        st.beta_to = beta
+        st.t0 = t0
+        run.sweep(st)
+        s1 = run.replica_spins(sample)
+        E1 = run.energies()
+        for n, r in enumerate(sample):
+            so, Eo = init_o[n]
+            o.sweep_replicas(dim, L, J, seed, beta, int(r), so, Eo, t0, 10)
+            assert np.array_equal(s1[n], so[0]) and E1[r] == Eo[0], f"replica {r} at beta={beta}"
+    note("C4 full size: resample 4.0 -> 4.0 + 1/60")
     old_buf = run.query().cur
     run.resample(sched.step(2))
     code, _ = run.status()
