@@ -391,6 +391,25 @@ def bench_gauss_stepped(args):
     print(json.dumps(out), flush=True)
 
 
+def first_look_regime(beta):
+    """Regime of the sweep's 16-bit first look at beta (3D, dE = 4, 8, 12): 0 while the top 16 bits
+    of the dE = 8 threshold are non-zero, 1 while only dE = 4 has a non-zero top, 2 beyond."""
+    top = lambda dE: int(np.floor(np.ldexp(np.exp(-beta * dE), 16)))  # noqa: E731
+    return 0 if top(8) > 0 else (1 if top(4) > 0 else 2)
+
+
+def sweep_by_regime(betas, sweep_ms, attempts):
+    """Mean sweep launch time and attempts/s per first-look regime over the timed steps."""
+    reg = np.array([first_look_regime(b) for b in betas])
+    out = {}
+    for r in (0, 1, 2):
+        sel = reg == r
+        if sel.any():
+            out[str(r)] = {"steps": int(sel.sum()), "avg_launch_ms": float(np.mean(sweep_ms[sel])),
+                           "attempts_per_s": float(np.sum(attempts[sel]) / (np.sum(sweep_ms[sel]) * 1e-3))}
+    return out
+
+
 def cpu_baseline(L, R0, n_sweeps, target_s):
     """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
     from oracle import oracle as o
@@ -519,6 +538,7 @@ def main():
                      "kernel": "k_sweep3f (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
                      "ops_per_attempt": OPS_PER_ATTEMPT},
         "sweep_attempts_per_s": per_launch_attempts / sweep_s,
+        "sweep_by_regime": sweep_by_regime(betas[ks], sweep_ms, R_steps * N * args.n_sweeps),
         "final_minus_betaF": float(rec[ks[-1], 2]),
     }
     if not args.no_cpu_baseline:

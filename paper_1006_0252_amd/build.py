@@ -1,7 +1,9 @@
 """Build libpa.so (HIP for gfx950) in-tree.
 
 Every .hip file under csrc/ is compiled to an object in parallel, then linked into
-paper_1006_0252_amd/libpa.so.  FP32 packed math is switched off for all device code.
+paper_1006_0252_amd/libpa.so; calib/ (the vector-ALU rate and clock probe that the benchmark's
+ALU roofline uses) is linked into paper_1006_0252_amd/libpa_calib.so.  FP32 packed math is
+switched off for all device code.
 """
 from __future__ import annotations
 
@@ -13,9 +15,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+CALIB = os.path.join(HERE, "calib")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpa.so")
+CALIB_LIB = os.path.join(HERE, "libpa_calib.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -31,8 +35,8 @@ FLAGS = [
 ]
 
 
-def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+def sources(d=CSRC):
+    return sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
@@ -44,21 +48,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link libpa.so; returns the library path."""
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    workers = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
-    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source, link libpa.so and libpa_calib.so; returns libpa.so's path."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    calib = sources(CALIB)
+    workers = max(1, min(len(srcs) + len(calib), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(_compile, srcs + calib))
+    _link(objs[: len(srcs)], LIB)
+    _link(objs[len(srcs):], CALIB_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {CALIB_LIB}")
     return LIB
 
 

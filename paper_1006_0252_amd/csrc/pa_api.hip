@@ -148,11 +148,11 @@ int pa_sweep(pa_run* runs, int n_runs, const pa_step* step)
         if (st != PA_OK) return st;
     }
     if (step->n_sweeps == 0) return PA_OK;
-    bool fast = batchable(runs, n_runs) && runs[0].dim == 3 && n_runs <= 1024;
+    SweepParams p;
+    build_sweep_params(*step, 6, &p);
+    bool fast = batchable(runs, n_runs) && runs[0].dim == 3 && n_runs <= 1024 && fast_sweep_thresholds_ok(p);
     for (int r = 0; fast && r < n_runs; ++r) fast = fast_sweep_supported(runs[r].dim, runs[r].L);
     if (fast) {
-        SweepParams p;
-        build_sweep_params(*step, 6, &p);
         st = launch_sweep_batch(runs, n_runs, p, (hipStream_t)runs[0].stream);
         if (st != PA_OK) return st;
         return hip_status(hipGetLastError());

@@ -118,6 +118,9 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
 int launch_free_energy(const pa_run* runs, int n, double* out, hipStream_t s);
 int launch_sweep_batch(const pa_run* runs, int n, const SweepParams& p, hipStream_t s);
 bool fast_sweep_supported(int dim, int L);
+// the fast cube sweep compares first looks against top + 1 in 16 bits: tops up to 0xFFFE (a move
+// of dE = 4 accepted with probability below 1 - 2^-16, i.e. beta above about 4e-6)
+inline bool fast_sweep_thresholds_ok(const SweepParams& p) { return p.thi[4] <= 0xFFFEu; }
 int build_sweep_params(const pa_step& step, int z, SweepParams* p);
 int launch_weighted_average_dev(int n_sets, int M, const double* x, const double* R, const double* A, int n_obs,
                                 double* out, hipStream_t s);

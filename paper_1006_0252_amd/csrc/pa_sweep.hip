@@ -527,7 +527,7 @@ int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
     SweepConfig cfg = default_config(run.dim, run.L);
     if (g_override.lpr) cfg = g_override;
     int st;
-    if (fast_sweep_supported(run.dim, run.L)) {
+    if (fast_sweep_supported(run.dim, run.L) && fast_sweep_thresholds_ok(p)) {
         SweepConfig fc = g_override.lpr ? g_override : fast_config(run.L);
         st = launch_sweep_fast(run, p, fc.lpr, fc.wpb, s);
         if (st != PA_OK) return st;

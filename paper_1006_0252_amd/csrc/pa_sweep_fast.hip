@@ -14,8 +14,12 @@
 //  - the 16-bit first look is done on pairs of sites with packed 16-bit ops, specialised by
 //    regime:  MODE 2: every threshold of c >= 4 has top 16 bits 0 (beta > ln 2^16 / 4): only
 //    u == 0 can accept, and that is a tie;  MODE 1: only c = 4 has a non-zero top;  MODE 0:
-//    general, the pair's thresholds from a 16-entry LDS table.  Possible ties are flagged per
-//    lane and resolved exactly with the 48 low bits in a separate (rare) path;
+//    general, the pair's thresholds from a 16-entry LDS table.  One saturated subtraction
+//    (top + 1) - u per site gives all three outcomes at once: 0 rejects, 1 is a tie (u equals
+//    the top), 2 or more accepts; clamped to 2, the two-bit outcomes of a row are packed into one
+//    word, whose low bits flag ties and whose high bits are the accepted sites.  Ties are
+//    resolved exactly with the 48 low bits in a separate (rare) path.  Tops of 0xFFFF and above
+//    (beta below 4e-6) do not leave room for the + 1 and take the generic kernel instead;
 //  - energies are recomputed once per launch from bond popcounts.
 //
 // Two launch forms share the per-tile code: one block of waves per group of replicas of one
@@ -110,7 +114,9 @@ struct FastLayout {
     static constexpr int JPAD = LPR == 4 ? 4 : 0;
     static constexpr int JSTRIDE = JROWS * 8 + JPAD;            // dwords of coupling masks per plane
     static constexpr int JDWORDS = L * JSTRIDE;
-    static constexpr int TDWORDS = 16;                          // pair-threshold table after the masks
+    // after the masks: the 16-entry pair-bound table, then (L = 0 mod 4) the 256-entry table of
+    // two consecutive pairs of a row (8-byte entries, so 8-byte aligned: JDWORDS is even)
+    static constexpr int TDWORDS = L % 4 == 0 ? 16 + 512 : 16;
     static constexpr int TAB_DWORDS = JDWORDS + TDWORDS;        // block-shared tables
     static constexpr int ROW_BYTES = L * PSTRIDE * 2;           // one wave's rows
     static constexpr size_t lds_bytes(int wpb) { return (size_t)TAB_DWORDS * 4 + (size_t)wpb * ROW_BYTES; }
@@ -140,20 +146,20 @@ __device__ void row_masks(const int8_t* J, int rho, uint32_t m[6])
 }
 
 // the block-shared tables: coupling masks per row pair (rows y and y + L/2 in one entry);
-// then the thresholds of a pair of sites by their class bits (two consecutive sites of a colour
-// in a row, or site m of both rows of a word when L/2 is odd): entry a + 4 b (a, b = c0 + 2 c1
-// of the first and second site) holds thi(a) | thi(b) << 16, with
-// class index 0, 1, 2 for c = 4, 5, 6 (3 cannot occur at a candidate site).  A threshold of
-// 0x10000 (always accept) is stored as 0xFFFF: every u below it accepts, and u = 0xFFFF equals
-// it, which flags a tie that the exact path settles with the true threshold
+// then the first-look bounds of a pair of sites by their class bits (two consecutive sites of a
+// colour in a row, or site m of both rows of a word when L/2 is odd): entry a + 4 b (a, b = c0 +
+// 2 c1 of the first and second site) holds (thi(a) + 1) | (thi(b) + 1) << 16, with class index 0,
+// 1, 2 for c = 4, 5, 6 (3 cannot occur at a candidate site).  The launch guarantees thi <= 0xFFFE.
 template <int L, int LPR>
 __device__ void build_jtab(const pa_state* st, uint32_t* jtab, const FastThr& th, int tid, int nthr)
 {
     using F = FastLayout<L, LPR>;
-    if (tid < F::TDWORDS) {
-        const uint32_t t[4] = {min(th.thi4, 0xFFFFu), min(th.thi5, 0xFFFFu), min(th.thi6, 0xFFFFu),
-                               min(th.thi6, 0xFFFFu)};
-        jtab[F::JDWORDS + tid] = t[tid & 3] | (t[tid >> 2] << 16);
+    const uint32_t t[4] = {th.thi4 + 1u, th.thi5 + 1u, th.thi6 + 1u, th.thi6 + 1u};
+    for (int e = tid; e < F::TDWORDS; e += nthr) {
+        // entry n < 16: the pair of class nibble n; entry 16 + 2n + h (n < 256): the pair of nibble
+        // h of byte n (the four class bits of the first pair, then of the second)
+        const int n = e < 16 ? e : (((e - 16) >> 1) >> (4 * ((e - 16) & 1))) & 15;
+        jtab[F::JDWORDS + e] = t[n & 3] | (t[n >> 2] << 16);
     }
     const int8_t* J = st->J;
     for (int e_i = tid; e_i < L * F::JROWS; e_i += nthr) {
@@ -174,6 +180,9 @@ struct PlaneCtx {
 };
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+// bits of a where m is set, of b elsewhere (one v_bfi_b32)
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
 
 // bit-sliced count of the six bond words: c = c0 + 2 c1 + 4 c2 bonds with J s_i s_j = -1 per bit
 __device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4,
@@ -215,8 +224,8 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
     const uint32_t cmA = m0 | ((Y % 2 ? m1 : m0) << 16);
     const uint32_t cmB = m1 | ((Y % 2 ? m0 : m1) << 16);
     static_assert(H % 2 == 1 || PH == 0, "paired fields need the plane to start a Philox call");
-    const u16x2 t4 = {(uint16_t)th.thi4, (uint16_t)th.thi4};
-    const u16x2 one = {1, 1};
+    const u16x2 t4 = {(uint16_t)(th.thi4 + 1u), (uint16_t)(th.thi4 + 1u)};
+    const u16x2 two = {2, 2};
     uint4v rndA = {0, 0, 0, 0}, rndB = {0, 0, 0, 0};
 #pragma unroll
     for (int yy = 0; yy < Y; ++yy) {
@@ -239,20 +248,25 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
         uint32_t flip;
         if constexpr (H % 2 == 0) {
             // sites m and m + 1 (m even) of a row take the two 16-bit fields of one Philox word:
-            // both are compared with packed 16-bit ops against their thresholds t (thi4 for c = 4
-            // and 0 above in MODE 1; from the pair table by the sites' class bits in MODE 0).  Per
-            // half: t - u saturated at 0 is non-zero iff u < t; u - t is zero iff u == t.  Accept
-            // bits are gathered at 2m + par (low field) and 16 + 2m + par (high field), then moved
-            // to 2m + 2 + par.
+            // both are compared with packed 16-bit ops against their bounds b = top + 1 (thi4 + 1
+            // in MODE 1, from the pair table by the sites' class bits in MODE 0): per half
+            // e = min(b - u saturated at 0, 2) is 0 (reject), 1 (tie) or 2 (accept).  The two-bit
+            // fields gather in one word: row A's at 2m (site m) and 16 + 2m (site m + 1), row B's two
+            // bits above those; afterwards the accept bits (the high bit of each field) move to the
+            // sites' own bits, site m of row A at 2m + par, site m + 1 at 2m + 2 + par, row B's 16
+            // bits higher.
             u16x2 zmin = {0xFFFF, 0xFFFF};
-            uint32_t rawA = 0, rawB = 0;
+            uint32_t raw = 0;
             // MODE 0: class bits of the colour's sites side by side, c0(x) at bit x and c1(x) at
-            // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par (+ 16).  With
-            // L = 16 the c1 bit of the high row's x = 15 would leave the word: that row takes c1(x)
-            // at bit x and c0(x) at bit x - 1 instead (the same nibble, one bit lower)
+            // bit x + 1, so the four bits of sites m, m + 1 are one nibble at 2m + par (+ 16), and
+            // the two pairs m, m + 2 one byte (one 8-byte entry of the 256-entry table).  With L = 16
+            // the c1 bit of the high row's x = 15 would leave the word: that row takes c1(x) at bit x
+            // and c0(x) at bit x - 1 instead (the same nibble, one bit lower)
             const uint32_t c01 = (c0 & colmask) | ((c1 << 1) & ~colmask);
             const uint32_t c01h = L == 16 ? ((c1 & colmask) | ((c0 >> 1) & ~colmask)) : c01;
             constexpr int OFFH = L == 16 ? 15 : 16;
+            const uint2* TT2 = reinterpret_cast<const uint2*>(TT + 16);
+            uint2 bA = {0, 0}, bB = {0, 0};
     #pragma unroll
             for (int m = 0; m < H; m += 2) {
                 const int hA = PH + yy * H + m, hB = PH + (yy + Y) * H + m;  // half-site positions from call cb
@@ -265,30 +279,45 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                 if (MODE == 2) {
                     zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
                 } else {
-                    const u16x2 tA = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01 >> (2 * m + par)) & 15u]);
-                    const u16x2 tB = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, TT[(c01h >> (OFFH + 2 * m + par)) & 15u]);
+                    if (MODE == 0 && m % 4 == 0) {  // the bounds of pairs m and m + 2 at once
+                        if (m + 2 < H) {
+                            bA = TT2[(c01 >> (2 * m + par)) & 255u];
+                            bB = TT2[(c01h >> (OFFH + 2 * m + par)) & 255u];
+                        } else {
+                            bA.x = TT[(c01 >> (2 * m + par)) & 15u];
+                            bB.x = TT[(c01h >> (OFFH + 2 * m + par)) & 15u];
+                        }
+                    }
+                    const u16x2 tA = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, m % 4 == 0 ? bA.x : bA.y);
+                    const u16x2 tB = MODE == 1 ? t4 : __builtin_bit_cast(u16x2, m % 4 == 0 ? bB.x : bB.y);
                     const u16x2 dA = __builtin_elementwise_sub_sat(tA, wA);
                     const u16x2 dB = __builtin_elementwise_sub_sat(tB, wB);
-                    // min(d, 1) per half, written out: as an expression the optimiser turns it into
-                    // d != 0, i.e. two compares, two selects and a byte permute per word
-                    uint32_t aA, aB;
-                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(aA) : "v"(dA), "v"(one));
-                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(aB) : "v"(dB), "v"(one));
-                    rawA |= aA << (2 * m + par);
-                    rawB |= aB << (2 * m + par);
-                    if (MODE == 1)
-                        zmin = __builtin_elementwise_min(
-                            zmin, __builtin_elementwise_min(__builtin_elementwise_min(wA - tA, wA),
-                                                            __builtin_elementwise_min(wB - tB, wB)));
-                    else
-                        zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA - tA, wB - tB));
+                    // min(d, 2) per half, written out: as an expression the optimiser may expand it
+                    // into compares and selects per half
+                    uint32_t eA, eB;
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(eA) : "v"(dA), "v"(two));
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(eB) : "v"(dB), "v"(two));
+                    raw |= eA << (2 * m);
+                    raw |= eB << (2 * m + 2);
+                    // MODE 1: classes 5 and 6 have top 0, so u == 0 is a tie there
+                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
                 }
             }
-            const bool tie = zmin.x == 0 || zmin.y == 0;
-            const uint32_t acc = (rawA & 0xFFFFu) | (rawA >> 14) | (((rawB & 0xFFFFu) | (rawB >> 14)) << 16);
-            if (MODE == 2) flip = colmask & ~c2;
-            else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
-            else flip = colmask & (~c2 | acc);
+            bool tie = zmin.x == 0 || zmin.y == 0;
+            if (MODE == 2) {
+                flip = colmask & ~c2;
+            } else {
+                if (MODE == 0) tie = (raw & 0x55555555u) != 0;  // the low (tie) bit of every field
+                else tie = tie || (raw & 0x55555555u) != 0;
+                // accept bits to the sites (m = 0, 2, 4, 6): row A's site m from 2m + 1 to 2m + par and
+                // row B's site m + 1 from 16 + 2m + 3 to 16 + 2m + 2 + par (right by 1 - par); row A's
+                // site m + 1 from 16 + 2m + 1 to 2m + 2 + par (right by 15 - par); row B's site m from
+                // 2m + 3 to 16 + 2m + par (left by 13 + par).  Only the colour's sites are kept.
+                const uint32_t s1 = (0x44441111u << par), s15 = 0x4444u << par;
+                const uint32_t acc = select_bits(s1, raw >> (1 - par), select_bits(s15, raw >> (15 - par), raw << (13 + par)));
+                if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+                else flip = colmask & (~c2 | acc);
+            }
             if (tie) {
                 const uint32_t cand = c2 & colmask;
                 const int rA = yy + L * z;  // the high row is rA + L/2
@@ -331,18 +360,25 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                     const u16x2 t = MODE == 1 ? t4
                                               : __builtin_bit_cast(u16x2, TT[((c01 >> xA) & 3u) | (((c01 >> xB) & 3u) << 2)]);
                     const u16x2 d = __builtin_elementwise_sub_sat(t, w);
-                    uint32_t a;  // min(d, 1) per half, written out (see above)
-                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(a) : "v"(d), "v"(one));
-                    raw |= a << (2 * m + par);
-                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(w - t, w));
-                    else zmin = __builtin_elementwise_min(zmin, w - t);
+                    uint32_t e;  // min(d, 2) per half, written out (see above)
+                    asm("v_pk_min_u16 %0, %1, %2" : "=v"(e) : "v"(d), "v"(two));
+                    raw |= e << (2 * m + par);
+                    if (MODE == 1) zmin = __builtin_elementwise_min(zmin, w);
                 }
             }
-            const bool tie = zmin.x == 0 || zmin.y == 0;
-            const uint32_t acc = (raw & 0xFFFFu) | ((raw >> (16 + par)) << (16 + parh));
-            if (MODE == 2) flip = colmask & ~c2;
-            else if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
-            else flip = colmask & (~c2 | acc);
+            bool tie = zmin.x == 0 || zmin.y == 0;
+            if (MODE == 2) {
+                flip = colmask & ~c2;
+            } else {
+                // fields at 2m + par (row A) and 16 + 2m + par (row B); accept bits one higher
+                const uint32_t f1 = 0x55555555u << par;
+                if (MODE == 0) tie = (raw & f1) != 0;
+                else tie = tie || (raw & f1) != 0;
+                // row A's site m to 2m + par, row B's to 16 + 2m + parh (parh = 1 - par)
+                const uint32_t acc = ((raw >> 1) & (0x5555u << par)) | ((raw >> (2 * par)) & (0x55550000u << parh));
+                if (MODE == 1) flip = colmask & (~c2 | (acc & ~c1 & ~c0));
+                else flip = colmask & (~c2 | acc);
+            }
             if (tie) {
                 const uint32_t cand = c2 & colmask;
                 const int rA = yy + L * z;  // the high row is rA + L/2
@@ -757,7 +793,7 @@ bool fast_sweep_supported(int dim, int L) { return dim == 3 && L % 2 == 0 && L >
 // returns PA_ERR_ARG when the lattice is not one the fast kernel handles
 int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s)
 {
-    if (!fast_sweep_supported(run.dim, run.L)) return PA_ERR_ARG;
+    if (!fast_sweep_supported(run.dim, run.L) || !fast_sweep_thresholds_ok(p)) return PA_ERR_ARG;
     int mode;
     const FastThr th = make_thr(p, &mode);
     switch (run.L) {
@@ -835,7 +871,7 @@ static void launch_group_L(int L, pa_state* base, int pos0, int pos1, const Batc
 // appearance), one work list over all groups, one persistent launch per group.
 int launch_sweep_batch(const pa_run* runs, int n_runs, const SweepParams& p, hipStream_t s)
 {
-    if (n_runs > kMaxBatch) return PA_ERR_ARG;
+    if (n_runs > kMaxBatch || !fast_sweep_thresholds_ok(p)) return PA_ERR_ARG;
     for (int r = 0; r < n_runs; ++r)
         if (batch_lds_bytes(runs[r].L) > fast_lds_limit()) return PA_ERR_ARG;
     // distinct sizes in order of first appearance, then (order 1) by tile cost, larger first

@@ -77,8 +77,11 @@ def test_init_with_host_couplings():
 
 
 # regimes: 0 (beta < 1.39), 1 (1.39 .. 2.77), 2.  At beta = 1e-17 exp(-4 beta) rounds to 1 (class
-# c = 4 always accepts) while c = 5, 6 have T64 = 2^64 - 2^11: first-look threshold 0xFFFF
-SWEEP_BETAS = [0.0, 1e-17, 0.35, 1.2, 2.0, 5.0]
+# c = 4 always accepts) while c = 5, 6 have T64 = 2^64 - 2^11: first-look threshold 0xFFFF.  The
+# fast cube kernel compares against top + 1 in 16 bits: at beta = 5e-6 the top of c = 4 is 0xFFFE
+# (the largest it takes), at 3e-6 it is 0xFFFF and the generic kernel sweeps instead (as at 0 and
+# 1e-17)
+SWEEP_BETAS = [0.0, 1e-17, 3e-6, 5e-6, 0.35, 1.2, 2.0, 5.0]
 
 
 @pytest.mark.parametrize("dim,L,layout,R0", INIT_CASES)
