@@ -65,6 +65,7 @@ extern "C" {
 #define PA_ERR_NONFINITE 4  /* normalisation sum S not finite or not positive */
 #define PA_ERR_HIP 5        /* HIP runtime error (launch, copy, synchronisation) */
 #define PA_ERR_NOT_INIT 6   /* run not initialised by pa_init_couplings */
+#define PA_ERR_SIZE 7       /* input larger than a fixed-size device scratch area holds */
 
 /* sticky device status bits (pa_status) */
 #define PA_FLAG_CAPACITY (1 << 0)
@@ -400,6 +401,18 @@ int pa_mlp_work_bytes(int64_t B, int64_t* bytes);
  * the batch are taken in a fixed order, so the result is reproducible. */
 int pa_mlp_grad(const uint16_t* w, const float* x, const double* target, int64_t B, void* work, float* grad,
                 float* loss, void* stream);
+
+/* pa_mlp_grad for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the same result, bit for
+ * bit, with the work matrix and partial gradients in a fixed device array of the library
+ * (PA_MLP_STATIC_MAX_B samples, 6.6 MB, held on each device from the first call until the process
+ * ends) instead of caller memory.  Allocates nothing.  B > PA_MLP_STATIC_MAX_B returns PA_ERR_SIZE
+ * before any device work.  Every call on a device shares that device's array: calls that overlap
+ * on one GPU (different streams, threads or processes' graphs) race and must be serialised by the
+ * caller. */
+#define PA_MLP_STATIC_MAX_B 4096
+int pa_mlp_grad_static(const uint16_t* w, const float* x, const double* target, int64_t B, float* grad, float* loss,
+                       void* stream);
 
 /* One Adam step (Kingma and Ba, ICLR 2015), step number t >= 1, on n FP32 master parameters
  * theta with moments m, v (device, zero before the first step): m = beta1 m + (1 - beta1) g,

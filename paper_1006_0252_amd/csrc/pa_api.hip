@@ -400,6 +400,7 @@ const char* pa_strerror(int code)
         case PA_ERR_NONFINITE: return "normalisation sum is not finite and positive";
         case PA_ERR_HIP: return "HIP runtime error";
         case PA_ERR_NOT_INIT: return "run not initialised";
+        case PA_ERR_SIZE: return "input larger than the fixed device scratch area holds";
         default: return "unknown status";
     }
 }

@@ -9,6 +9,8 @@
 // so every schedule the network produces is an exact schedule.
 #include <math.h>
 
+#include <mutex>
+
 #include "pa_common.h"
 
 namespace pa {
@@ -385,6 +387,48 @@ int launch_rho(const pa_run* runs, int n, const double* args, int n_args, int mo
     return hip_status(hipGetLastError());
 }
 
+// The loss gradient of a batch of at most kStaticMaxB samples with its work matrix and partial
+// gradients in a fixed device array instead of caller memory, for callers that cannot allocate.
+// Every call on a device shares that device's array: calls that overlap on one GPU race.  Nothing
+// in it needs clearing between calls (every element a call reads, it has written first).
+constexpr int64_t kStaticMaxB = 4096;
+constexpr int64_t kStaticFloats = (int64_t)kRows * kStaticMaxB + ((kStaticMaxB + kChunk - 1) / kChunk) * (kParams + 1);
+static __device__ __align__(256) float scratch[kStaticFloats];
+
+constexpr int kMaxDevices = 64;
+static float* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device, once looked up
+static std::mutex g_scratch_lock;
+
+// the current device's address of `scratch` (the host-side name is not a device address)
+static int scratch_address(float** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PA_ERR_HIP;
+    std::lock_guard<std::mutex> g(g_scratch_lock);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PA_ERR_HIP;
+        g_scratch_dev[dev] = (float*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return PA_OK;
+}
+
+// the kernels of pa_mlp_grad on a given work area
+static int mlp_grad_launch(const uint16_t* w, const float* x, const double* target, int64_t B, float* wk, float* grad,
+                           float* loss, hipStream_t s)
+{
+    float* partial = wk + (int64_t)kRows * mlp_ld(B);
+    const int64_t nc = mlp_chunks(B);
+    if (nc > 65535) return PA_ERR_ARG;
+    hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, w, x, B, 0.0f, 0.0f,
+                       (float*)nullptr, target, wk);
+    hipLaunchKernelGGL(k_mlp_grad_partial, dim3(4, (unsigned)nc), dim3(256), 0, s, (const float*)wk, B, partial);
+    hipLaunchKernelGGL(k_mlp_grad_sum, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, (const float*)partial,
+                       (int)nc, grad, loss);
+    return hip_status(hipGetLastError());
+}
+
 }  // namespace pa
 
 using namespace pa;
@@ -410,17 +454,18 @@ extern "C" int pa_mlp_grad(const uint16_t* w, const float* x, const double* targ
                            float* grad, float* loss, void* stream)
 {
     if (!w || !x || !target || !work || !grad || B <= 0 || B > ((int64_t)1 << 30)) return PA_ERR_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    float* wk = (float*)work;
-    float* partial = wk + (int64_t)kRows * mlp_ld(B);
-    const int64_t nc = mlp_chunks(B);
-    if (nc > 65535) return PA_ERR_ARG;
-    hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, s, w, x, B, 0.0f, 0.0f,
-                       (float*)nullptr, target, wk);
-    hipLaunchKernelGGL(k_mlp_grad_partial, dim3(4, (unsigned)nc), dim3(256), 0, s, (const float*)wk, B, partial);
-    hipLaunchKernelGGL(k_mlp_grad_sum, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, (const float*)partial,
-                       (int)nc, grad, loss);
-    return hip_status(hipGetLastError());
+    return mlp_grad_launch(w, x, target, B, (float*)work, grad, loss, (hipStream_t)stream);
+}
+
+extern "C" int pa_mlp_grad_static(const uint16_t* w, const float* x, const double* target, int64_t B, float* grad,
+                                  float* loss, void* stream)
+{
+    if (!w || !x || !target || !grad || B <= 0) return PA_ERR_ARG;
+    if (B > kStaticMaxB) return PA_ERR_SIZE;
+    float* wk = nullptr;
+    const int st = scratch_address(&wk);
+    if (st != PA_OK) return st;
+    return mlp_grad_launch(w, x, target, B, wk, grad, loss, (hipStream_t)stream);
 }
 
 extern "C" int pa_mlp_adam(float* theta, float* m, float* v, const float* grad, uint16_t* w, int64_t n, int t,

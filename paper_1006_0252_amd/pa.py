@@ -15,7 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpa.so")
 
-PA_OK, PA_ERR_ARG, PA_ERR_CAPACITY, PA_ERR_EXTINCT, PA_ERR_NONFINITE, PA_ERR_HIP, PA_ERR_NOT_INIT = range(7)
+PA_OK, PA_ERR_ARG, PA_ERR_CAPACITY, PA_ERR_EXTINCT, PA_ERR_NONFINITE, PA_ERR_HIP, PA_ERR_NOT_INIT, PA_ERR_SIZE = range(8)
+PA_MLP_STATIC_MAX_B = 4096
 PA_FLAG_CAPACITY, PA_FLAG_EXTINCT, PA_FLAG_NONFINITE = 1, 2, 4
 PA_U8, PA_BITS64 = 0, 1
 LAYOUTS = {"u8": PA_U8, "bits64": PA_BITS64}
@@ -96,6 +97,7 @@ SIGNATURES = {
     "pa_mlp_forward": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
     "pa_mlp_work_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "pa_mlp_grad": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, P, P, P]),
+    "pa_mlp_grad_static": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, P, P]),
     "pa_mlp_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, P]),
     "pa_bf16_round": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
