@@ -34,8 +34,13 @@ METRIC = "spin-flip attempts/s at L=16; wall time to var(βF)≤1e-3, learned vs
 # (10 rounds x (2 wide multiplies + 2 three-input xors) = 40 ops per call, 8 attempts per call)
 # plus the threshold select, compare and flip (3 ops)
 OPS_PER_ATTEMPT = 40 / 8 + 3
-# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-ops per second
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X vector ALU from its unit counts and clock: the published FP32 vector peak, 157.3 TFLOP/s,
+# is 256 CUs x 2.4 GHz x 128 lanes x 2 flops (one FMA); the same 128 32-bit lanes per clock per CU
+# give 78.6 T int32 lane-ops/s.  (The probe in libpa_calib.so reaches ~100 lanes per clock per CU
+# with two-operand adds and xors at the clock the chip sustains under load; 64-bit multiplies and
+# three-operand ops issue at about half that.)
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
+COUNTERS = os.path.join(ROOT, "profiles", "sweep_L16_R1e6_counters.json")
 
 
 def parse():
@@ -61,7 +66,11 @@ def parse():
                         "gauss: the Gaussian 3D ensemble, L=8, R=2000, 100 temperatures, 100 sweeps, 126 runs; "
                         "gauss_survey: 25 Gaussian L=8 realizations (Var(beta F~) vs Gamma) and the worst at R=2000 and 10000; "
                         "gauss_stepped: constant R=2000 vs R_beta 1000/3000 (beta_c=0.9) on the worst Gaussian realization")
-    p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned workload)")
+    p.add_argument("--ensemble", type=int, default=100, help="runs per schedule (learned vs fixed)")
+    p.add_argument("--no-learned", action="store_true", help="skip the learned-vs-fixed leg of the default run")
+    p.add_argument("--no-probe", action="store_true", help="skip the live vector-ALU probe of the default run")
+    p.add_argument("--oracle-runs", action="store_true",
+                   help="time whole oracle runs of the ring and of the L=8 cube on the host, then exit")
     return p.parse_args()
 
 
@@ -91,6 +100,13 @@ def bench_batched(args):
 
 
 def bench_learned(args):
+    """The learned-vs-fixed protocol (learned_vs_fixed) as the benchmark line: value = best fixed
+    time to target / best learned time to target."""
+    out = learned_vs_fixed(args.ensemble)
+    print(json.dumps(out), flush=True)
+
+
+def learned_vs_fixed(M):
     """Learned vs fixed temperature steps on the 3D +-J cube L = 12, R0 = 2e5, 10 sweeps per
     temperature, beta 0 -> 5, one coupling realization (disorder seed 1).
 
@@ -106,7 +122,7 @@ def bench_learned(args):
     from paper_1006_0252_amd import learned, pa
 
     dev = "cuda:0"
-    L, R0, ns, M = 12, 200_000, 10, args.ensemble
+    L, R0, ns = 12, 200_000, 10
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.perf_counter()
     Xt, Dt, Xv, Dv = learned.training_set(device=dev)
@@ -162,22 +178,15 @@ def bench_learned(args):
                      "validation_samples": int(Xv.shape[0]),
                      "final_loss": {str(rs): [h[-1][1], h[-1][2]] for rs, h in logs.items()}},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
-
-SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_fast.hip", "paper_1006_0252_amd/csrc/pa_sweep_util.h",
-                 "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
 
 
 def sweep_source_digest():
     """sha256 over the sources the sweep kernel is compiled from."""
-    import hashlib
+    from paper_1006_0252_amd.profile_summary import sweep_source_digest as digest
 
-    h = hashlib.sha256()
-    for rel in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    return digest()
 
 
 def sweep_traffic(path):
@@ -410,32 +419,126 @@ def sweep_by_regime(betas, sweep_ms, attempts):
     return out
 
 
-def cpu_baseline(L, R0, n_sweeps, target_s):
-    """The oracle's pa_sweep on the first replicas of the same initial population, beta = 1."""
-    from oracle import oracle as o
+def cpu_info():
+    """Model name and logical CPUs available to this process."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
 
+
+def oracle_sweep_rate(o, L, n_sweeps, beta, target_s, max_replicas):
+    """The oracle's sweep of the first replicas of the L-cube's initial population (disorder seed 1,
+    run seed 1): attempts/s on the oracle's current threads, on about target_s seconds of work."""
     dim = 3
     J = o.couplings(dim, L, 1)
     threads = o.num_threads()
     n = max(threads, 16)
     s, E = o.init_replicas(dim, L, J, 1, 0, n)
     t = time.perf_counter()
-    o.sweep_replicas(dim, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
-    dt = time.perf_counter() - t
-    per_rep = dt / n
-    m = int(min(R0, max(threads, target_s / max(per_rep, 1e-9))))
+    o.sweep_replicas(dim, L, J, 1, beta, 0, s, E, 0, n_sweeps)
+    per_rep = (time.perf_counter() - t) / n
+    m = int(min(max_replicas, max(threads, target_s / max(per_rep, 1e-9))))
     s, E = o.init_replicas(dim, L, J, 1, 0, m)
     t = time.perf_counter()
-    o.sweep_replicas(dim, L, J, 1, 1.0, 0, s, E, 0, n_sweeps)
+    o.sweep_replicas(dim, L, J, 1, beta, 0, s, E, 0, n_sweeps)
     dt = time.perf_counter() - t
-    attempts = m * L ** 3 * n_sweeps
-    return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle sweep of the first {m} replicas of the L={L} population, {n_sweeps} sweeps at "
-                      f"beta=1 ({attempts:.3e} attempts in {dt:.1f} s)"}
+    return m * L ** 3 * n_sweeps / dt, m, dt
+
+
+def cpu_baseline(L, R0, n_sweeps, target_s):
+    """The oracle on this host: its pa_sweep (10 sweeps) on the first replicas of the benchmark's
+    own population at beta = 1 (the value, all threads) and beta = 5, and at beta = 1 on one
+    thread; plus one whole run of the ring configuration (N = 64, R0 = 1000, 51 temperatures, 5
+    sweeps)."""
+    from oracle import oracle as o
+
+    model, nproc = cpu_info()
+    threads = o.num_threads()
+    v1, m1, dt1 = oracle_sweep_rate(o, L, n_sweeps, 1.0, target_s, R0)
+    v5, m5, dt5 = oracle_sweep_rate(o, L, n_sweeps, 5.0, target_s / 2, R0)
+    o.set_num_threads(1)
+    try:
+        vs, ms, dts = oracle_sweep_rate(o, L, n_sweeps, 1.0, target_s / 4, R0)
+    finally:
+        o.set_num_threads(threads)
+    c1 = oracle_ring_run(o)
+    return {"value": v1, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle sweep of the first {m1} replicas of the L={L} population, {n_sweeps} sweeps at "
+                      f"beta=1 ({m1 * L ** 3 * n_sweeps:.3e} attempts in {dt1:.1f} s)",
+            "beta5": {"value": v5, "cores": threads, "replicas": m5, "seconds": dt5},
+            "one_core": {"value": vs, "cores": 1, "replicas": ms, "seconds": dts, "beta": 1.0},
+            "ring_full_run": c1, "cpu_model": model, "logical_cpus": nproc}
+
+
+def oracle_ring_run(o):
+    """One whole oracle run of the ring configuration: N = 64, R0 = 1000, 51 temperatures, 5 sweeps."""
+    J = o.couplings(1, 64, 1)
+    betas = [5.0 * k / 50 for k in range(51)]
+    t = time.perf_counter()
+    st, rec, _, _ = o.run(1, 64, J, 1, 1000, betas, 5)
+    dt = time.perf_counter() - t
+    attempts = float(rec[1:, 1].sum()) * 64 * 5
+    return {"seconds": dt, "attempts": attempts, "attempts_per_s": attempts / dt, "status": int(st),
+            "cores": o.num_threads()}
+
+
+def oracle_full_runs(args):
+    """--oracle-runs: whole oracle runs of the ring (N = 64, R0 = 1000, 51 temperatures, 5 sweeps)
+    and of the L = 8 cube (R0 = 5e4, 101 temperatures, 10 sweeps) on all threads; minutes of CPU."""
+    from oracle import oracle as o
+
+    model, nproc = cpu_info()
+    out = {"cpu_model": model, "logical_cpus": nproc, "threads": o.num_threads(), "ring": oracle_ring_run(o)}
+    J = o.couplings(3, 8, 1)
+    betas = [5.0 * k / 100 for k in range(101)]
+    t = time.perf_counter()
+    st, rec, _, _ = o.run(3, 8, J, 1, 50_000, betas, 10)
+    dt = time.perf_counter() - t
+    attempts = float(rec[1:, 1].sum()) * 512 * 10
+    out["cube_L8"] = {"seconds": dt, "attempts": attempts, "attempts_per_s": attempts / dt, "status": int(st)}
+    print(json.dumps(out), flush=True)
+
+
+def issue_ceilings():
+    """Live probe of the vector ALU (libpa_calib.so): lane-instructions/s of a few instruction kinds
+    and the engine clock the probe ran at."""
+    from paper_1006_0252_amd import valu_calibration as vc
+
+    res = vc.measure(kinds=[0, 1, 2, 5], iters=8000, repeats=2)
+    return {"clock_ghz": float(np.median([v["clock_hz"] for v in res.values()])) / 1e9,
+            "lane_instr_per_s": {k: v["rate"] for k, v in res.items()},
+            "lanes_per_clock_per_cu": {k: v["per_cu_per_clock"] for k, v in res.items()}}
+
+
+def counted_valu(path):
+    """VALU instructions per attempt of the sweep per first-look regime, from the committed
+    counter summary, or None when the sweep sources changed since it was taken."""
+    try:
+        with open(path) as f:
+            c = json.load(f)
+    except (ValueError, OSError):
+        return None
+    if c.get("source_digest") != sweep_source_digest():
+        return None
+    return c.get("valu_per_attempt")
 
 
 def main():
     args = parse()
+    if args.oracle_runs:
+        oracle_full_runs(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing to do", file=sys.stderr)
         sys.exit(2)
@@ -536,13 +639,40 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                      "kernel": "k_sweep3f (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
-                     "ops_per_attempt": OPS_PER_ATTEMPT},
+                     "ops_per_attempt": OPS_PER_ATTEMPT,
+                     "peak_basis": "256 CUs x 128 lanes x 2.4 GHz (FP32 vector 157.3 TFLOP/s / 2)",
+                     "hbm_frac": (traffic / sweep_s / 8e12) if traffic else None},
         "sweep_attempts_per_s": per_launch_attempts / sweep_s,
         "sweep_by_regime": sweep_by_regime(betas[ks], sweep_ms, R_steps * N * args.n_sweeps),
         "final_minus_betaF": float(rec[ks[-1], 2]),
     }
+    valu = counted_valu(COUNTERS)
+    for r, v in out["sweep_by_regime"].items():
+        v["frac"] = v["attempts_per_s"] * OPS_PER_ATTEMPT / PEAK_LANE_OPS
+        if valu and r in valu:
+            v["valu_per_attempt"] = valu[r]
+            v["valu_lane_instr_per_s"] = v["attempts_per_s"] * valu[r]
+    if not args.no_probe:
+        probe = issue_ceilings()
+        mix = probe["lane_instr_per_s"]["mad_u64+bitop3"]
+        for v in out["sweep_by_regime"].values():
+            if "valu_lane_instr_per_s" in v:
+                v["issue_frac_of_philox_mix"] = v["valu_lane_instr_per_s"] / mix
+        out["roofline"]["probe"] = probe
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.L, args.R0, args.n_sweeps, args.cpu_seconds)
+    if not args.no_learned:
+        del run, sched
+        torch.cuda.empty_cache()
+        lf = learned_vs_fixed(args.ensemble)
+        out["learned_vs_fixed"] = {
+            "workload": lf["config"]["workload"], "runs_per_schedule": args.ensemble,
+            "fixed_over_learned_time_to_target": lf["value"],
+            "best_learned": lf["best_learned"], "best_fixed": lf["best_fixed"],
+            "time_to_target_s": {**{f"learned_rho{k}": v["time_to_target_s"] for k, v in lf["learned"].items()},
+                                 **{f"fixed_nT{k}": v["time_to_target_s"] for k, v in lf["fixed"].items()}},
+            "learned_minus_reference_sigma": lf["learned_minus_reference_sigma"],
+            "training_seconds": lf["training"]["train_seconds"]}
     print(json.dumps(out), flush=True)
 
 

@@ -75,6 +75,8 @@ def lib():
         L.orc_overlap_average.argtypes = [i32, P, P, P, P]
         L.orc_run.argtypes = [i32, i32, P, u64, i64, i32, P, P, i32, i64, P, P, P, P]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
         L.orc_expd.argtypes = [f64]
         L.orc_expd.restype = f64
         L.orc_couplings_gauss.argtypes = [i32, i32, u64, P]
@@ -278,6 +280,11 @@ def run(dim, L, J, seed, R0, betas, ns, capacity=None, R_targets=None):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def bootstrap(x, idx, A=None, R=None):

@@ -884,6 +884,16 @@ int orc_run_gauss(int dim, int L, const double* J, uint64_t seed, int64_t R0, in
     return status;
 }
 
+/* threads for the oracle's parallel loops from now on (n >= 1) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* number of OpenMP threads the oracle's parallel loops use */
 int orc_num_threads(void)
 {

@@ -1,0 +1,142 @@
+"""Summaries of rocprofv3 outputs for the sweep's roofline (the files under profiles/).
+
+counters DIR... OUT: rocprofv3 --pmc passes over profile_sweep.py (one sweep launch per first-look
+    regime on the L = 16 cube, R0 = 1e6: beta = 0.5, 2, 4).  Per regime: every counter of the
+    sweep kernel's dispatch, and per attempt the lane-weighted counts (counter x 64 / attempts) of
+    the instruction counters.  Writes OUT (JSON, with the sha256 of the sweep's sources, which
+    bench.py checks before it uses the figures).
+traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR OUT: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) of the sweep in the benchmark, scaled by what the same counters read for a plain
+    device copy of known size (copy_calibration.py), as bytes per sweep launch.
+stats DIR: the kernel_stats table of a --kernel-trace --stats run as markdown.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_fast.hip", "paper_1006_0252_amd/csrc/pa_sweep_util.h",
+                 "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
+SWEEP_KERNEL = "k_sweep3f<16"
+ATTEMPTS_PER_LAUNCH = 1_000_000 * 4096 * 10  # profile_sweep.py: R0 = 1e6 replicas, L = 16, 10 sweeps
+INSTRUCTION_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VALU_INT32",
+                        "SQ_INSTS_VALU_INT64", "SQ_INSTS_SMEM", "SQ_INSTS_BRANCH")
+
+
+def sweep_source_digest():
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _rows(d, suffix):
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    out = []
+    for fn in files:
+        with open(fn) as f:
+            out += list(csv.DictReader(f))
+    return out
+
+
+def dispatch_counters(d, kernel):
+    """{dispatch id: {counter: value}} of the dispatches of `kernel` (substring of the name), in
+    dispatch order."""
+    per = {}
+    for r in _rows(d, "counter_collection.csv"):
+        if kernel not in r.get("Kernel_Name", ""):
+            continue
+        did = int(r["Dispatch_Id"])
+        per.setdefault(did, {})
+        name = r["Counter_Name"]
+        per[did][name] = per[did].get(name, 0.0) + float(r["Counter_Value"])
+    return dict(sorted(per.items()))
+
+
+def counters(dirs, out):
+    regimes = {}
+    for d in dirs:
+        disp = list(dispatch_counters(d, SWEEP_KERNEL).values())
+        if len(disp) != 3:
+            raise RuntimeError(f"{d}: expected 3 sweep dispatches (one per regime), found {len(disp)}")
+        for reg, c in enumerate(disp):
+            regimes.setdefault(str(reg), {}).update(c)
+    per_attempt = {r: {k: v * 64 / ATTEMPTS_PER_LAUNCH for k, v in c.items() if k in INSTRUCTION_COUNTERS}
+                   for r, c in regimes.items()}
+    res = {"kernel": "k_sweep3f<16, bits64> (pa_sweep, 10 sweeps per launch)",
+           "workload": "cube L=16, R0=1e6, bit-packed; one launch each at beta = 0.5, 2, 4 (first-look regimes 0, 1, 2)",
+           "attempts_per_launch": ATTEMPTS_PER_LAUNCH, "counters": regimes, "per_attempt": per_attempt,
+           "valu_per_attempt": {r: v["SQ_INSTS_VALU"] for r, v in per_attempt.items() if "SQ_INSTS_VALU" in v},
+           "source_digest": sweep_source_digest()}
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res["valu_per_attempt"]))
+
+
+def _kib(d, kernel, name):
+    disp = dispatch_counters(d, kernel)
+    vals = [c[name] for c in disp.values() if name in c]
+    if not vals:
+        raise RuntimeError(f"{d}: no {name} for {kernel}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out, copy_bytes=1 << 30):
+    f_kib, nf = _kib(fetch_dir, SWEEP_KERNEL, "FETCH_SIZE")
+    w_kib, nw = _kib(write_dir, SWEEP_KERNEL, "WRITE_SIZE")
+    # the copy kernel: the one whose dispatches read the most (torch's elementwise copy)
+    cf = dispatch_counters(copy_fetch_dir, "")
+    cw = dispatch_counters(copy_write_dir, "")
+    copy_f = max(c.get("FETCH_SIZE", 0.0) for c in cf.values())
+    copy_w = max(c.get("WRITE_SIZE", 0.0) for c in cw.values())
+    fs, ws = copy_bytes / (copy_f * 1024), copy_bytes / (copy_w * 1024)
+    res = {"kernel": "k_sweep3f<16, bits64> (pa_sweep, 10 sweeps per launch)",
+           "workload": "cube L=16, R0=1e6, bit-packed, the first steps of the 301-temperature schedule",
+           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
+           "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes, "fetch_kib_read": copy_f,
+                                "write_kib_read": copy_w, "fetch_scale": fs, "write_scale": ws},
+           "bytes_per_launch": f_kib * 1024 * fs + w_kib * 1024 * ws,
+           "source_digest": sweep_source_digest()}
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps({k: res[k] for k in ("fetch_kib_per_dispatch", "write_kib_per_dispatch", "bytes_per_launch")}))
+
+
+def stats(d):
+    rows = _rows(d, "kernel_stats.csv")
+    print("| kernel | calls | avg us | min us | max us | % of GPU time |")
+    print("|---|---|---|---|---|---|")
+    for r in rows:
+        name = r["Name"][:72]
+        print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+              f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+
+
+def main(argv):
+    if not argv:
+        print(__doc__)
+        return 2
+    cmd, rest = argv[0], argv[1:]
+    if cmd == "counters":
+        counters(rest[:-1], rest[-1])
+    elif cmd == "traffic":
+        traffic(*rest)
+    elif cmd == "stats":
+        stats(rest[0])
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
