@@ -83,6 +83,12 @@ def bench_batched(args):
     specs = workloads.batched_specs()
     r = ensemble.run_batched(specs, workloads.C3_TEMPS, workloads.C3_SWEEPS, tune=True, graph=True)
     w = r["weighted"]
+    rec = r["records"]
+    groups = {}
+    for i, sp in enumerate(specs):  # sweep attempts of the schedule per lattice size
+        g = groups.setdefault(str(sp["L"]), {"runs": 0, "attempts": 0.0})
+        g["runs"] += 1
+        g["attempts"] += float(np.sum(rec[i, 1:, 4])) * sp["L"] ** 3 * workloads.C3_SWEEPS
     out = {
         "metric": METRIC, "value": r["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1,
         "steps": workloads.C3_TEMPS - 1, "warmup": 0,
@@ -94,7 +100,8 @@ def bench_batched(args):
         "batched": {"attempts": r["attempts"], "seconds": r["seconds"],
                     "mean_var_betaF": float(np.mean(w["var_betaF"])),
                     "max_var_betaF": float(np.max(w["var_betaF"])),
-                    "mean_gamma": float(np.mean(w["gamma"])), "mean_binder": float(np.mean(w["binder"]))},
+                    "mean_gamma": float(np.mean(w["gamma"])), "mean_binder": float(np.mean(w["binder"])),
+                    "groups": groups},
     }
     print(json.dumps(out), flush=True)
 

@@ -68,23 +68,28 @@ def _time(fn, stream, repeats):
     return best
 
 
-def tune_batch(batch: "pa.Batch", step: "pa.pa_step", repeats: int = 2, verbose: bool = False):
-    """Pick the persistent-sweep schedule for this batch; returns (best, timings ms)."""
+def tune_batch(batch: "pa.Batch", steps, repeats: int = 2, verbose: bool = False):
+    """Pick the persistent-sweep schedule for this batch; returns (best, timings ms).  steps: one
+    pa_step or a list of them (e.g. one per first-look regime of the schedule); a candidate's time
+    is the sum over the steps of its best sweep time."""
+    steps = list(steps) if isinstance(steps, (list, tuple)) else [steps]
     st = batch.stream
     snap = _snapshot(batch.runs, st)
     timings, ref = {}, None
     for cand in BATCH_CANDIDATES:
         pa.set_batch_config(*cand)
+        t = 0.0
+        for step in steps:
+            def one(step=step):
+                batch.sweep(step)
 
-        def one():
-            batch.sweep(step)
-
-        t = float("inf")
-        for _ in range(repeats):
-            _restore(batch.runs, snap, st)
-            t = min(t, _time(one, st, 1))
+            best = float("inf")
+            for _ in range(repeats):
+                _restore(batch.runs, snap, st)
+                best = min(best, _time(one, st, 1))
+            t += best
         _restore(batch.runs, snap, st)
-        batch.sweep(step)
+        batch.sweep(steps[0])
         d = _digest(batch.runs)
         if ref is None:
             ref = d

@@ -61,7 +61,9 @@ def run_batched(specs, n_temps, n_sweeps, layout="bits64", device="cuda", tune=T
     torch.cuda.synchronize()
     tuned = None
     if tune:
-        tuned, timings = autotune.tune_batch(batch, sched.step(1), verbose=verbose)
+        # one step in each first-look regime of the schedule (beta near 0, about 2 and about 4)
+        ks = sorted({1, min(n_temps - 1, max(1, round(0.4 * (n_temps - 1)))), n_temps - 1 - (n_temps - 1) // 5})
+        tuned, timings = autotune.tune_batch(batch, [sched.step(k) for k in ks], verbose=verbose)
     ks = range(1, n_temps)
     if graph:
         g = batch.capture(sched, ks, pairs=True)
