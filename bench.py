@@ -645,7 +645,7 @@ def main():
                    "steps_timed": f"k={ks[0]}..{ks[-1]}", "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                     "kernel": "k_sweep3f (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
+                     "kernel": "k_sweep16c (pa_sweep, 10 fused sweeps)", "avg_launch_ms": sweep_s * 1e3,
                      "ops_per_attempt": OPS_PER_ATTEMPT,
                      "peak_basis": "256 CUs x 128 lanes x 2.4 GHz (FP32 vector 157.3 TFLOP/s / 2)",
                      "hbm_frac": (traffic / sweep_s / 8e12) if traffic else None},

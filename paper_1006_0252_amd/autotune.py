@@ -17,7 +17,8 @@ from . import pa
 # (blocks per CU, group order, launch form) of the batched sweep
 BATCH_CANDIDATES = ([(b, o, 0) for b in (8, 16, 24) for o in (0, 1)] + [(b, 1, 1) for b in (8, 16)] +
                     [(16, o, 2) for o in (0, 1)])
-SOLO_CANDIDATES = [(1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (4, 2), (4, 4)]
+# (0, 0): the library's default (for the bit-packed L = 16 cube its colour-packed kernel)
+SOLO_CANDIDATES = [(0, 0), (1, 1), (1, 2), (1, 4), (2, 2), (2, 4), (4, 2), (4, 4)]
 
 
 def _snapshot(runs, stream):
@@ -106,7 +107,8 @@ def tune_batch(batch: "pa.Batch", steps, repeats: int = 2, verbose: bool = False
 
 
 def tune_solo(run: "pa.Run", step: "pa.pa_step", repeats: int = 2, verbose: bool = False):
-    """Pick lanes per replica and waves per block for one run; returns (best, timings ms)."""
+    """Pick lanes per replica and waves per block for one run (or the default kernel, (0, 0));
+    returns (best, timings ms)."""
     st = run.stream
     snap = _snapshot([run], st)
     timings, ref = {}, None

@@ -111,6 +111,8 @@ int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s);
 // n > 1 chain runs (dim 1) with consecutive states, one length and layout, one stream
 int launch_sweep_chain_batch(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
 int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s);
+// the colour-packed kernel of the bit-packed L = 16 cube (PA_ERR_ARG for any other run)
+int launch_sweep_colour(const pa_run& run, const SweepParams& p, hipStream_t s);
 // batched launchers: n runs whose device states are contiguous (runs[r].state == runs[0].state + r)
 int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
 int launch_hist(const pa_run* runs, int n, hipStream_t s);

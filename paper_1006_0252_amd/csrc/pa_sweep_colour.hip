@@ -1,0 +1,478 @@
+// Metropolis sweeps of the L = 16 cube, bit-packed populations, with every bit of a 32-bit LDS word
+// a site of one colour: the same sample as the generic kernel (same Philox fields, same
+// acceptance rule, same checkerboard order), with half the bond-count work per attempt of the
+// row-pair kernel (whose words carry both colours).
+//
+// Word layout.  A replica's plane z is eight words W(sigma, rho, h): byte i (0..3) of W holds the
+// row y = rho + 2 i + 8 h, bit k (0..7) of that byte the site x = 2 k + sigma.  Every site of a word
+// has colour (sigma + rho + z) mod 2, so a colour phase of plane z updates the four words with
+// sigma + rho = col + z (mod 2), and every neighbour word is one of the other colour:
+//  - x: the word W(1 - sigma, rho, h) holds the x-neighbour on one side bit for bit, the other side
+//    is the same word with each byte rotated by one bit (left for sigma = 0, right for sigma = 1);
+//  - y: W(sigma, 1 - rho, h) holds one y-neighbour bit for bit, the other is the byte-shifted funnel
+//    of W(sigma, 1 - rho, h) and W(sigma, 1 - rho, 1 - h) (one v_alignbit_b32);
+//  - z: W(sigma, rho, h) of planes z + 1 and z - 1, bit for bit.
+// Row y's eight sites of a colour are the eight 16-bit fields of Philox call 16 z + y (field k for
+// site x = 2 k + sigma), so a word takes four whole calls.
+//
+// First look (Sec. II, the Metropolis rule with exact 64-bit thresholds): per Philox word the two
+// fields are compared at once with packed 16-bit ops against bounds top + 1 looked up by the class
+// bits of four sites; min(saturated(bound - u), 2) gives 0 (reject), 1 (tie: u equals the top) or 2
+// (accept).  The two-bit outcomes of rows 0, 1 and of rows 2, 3 gather in two words, placed so
+// that the accept bits reach their sites' bit positions with three shifts and three bit-field
+// selects.  Ties are resolved exactly with the 48 low bits in a separate (rare) path.  When every
+// top of a class c >= 4 is zero (beta above ln 2^16 / 4) only u = 0 can accept; the table is not
+// needed and a running minimum of the fields finds the ties.
+//
+// Launch: one block of four waves per 64-replica bit-packed group; a wave holds 16 replicas, four
+// lanes per replica, lane j taking planes 4 j .. 4 j + 3 (so the plane parity, and with it which
+// words a phase updates, is the same over the wave).  All LDS is static, so table offsets fold into
+// the instructions' immediate offsets.
+#include "pa_common.h"
+#include "pa_sweep_util.h"
+
+namespace pa {
+
+namespace colour {
+
+constexpr int L = 16;
+constexpr int NR = L * L;           // rows per replica
+constexpr int RPW = 16;             // replicas per wave
+constexpr int WPB = 4;              // waves per block: one 64-replica group
+constexpr int PS = 8 * RPW + 4;     // dwords per plane of a wave (eight words per replica; padding
+                                    // staggers the four lanes of a replica over the banks)
+constexpr int ROWW = L * PS;        // dwords of a wave's rows
+constexpr int JS = 8 * 6 + 2;       // dwords of coupling masks per plane (six per word)
+
+// thresholds by class c = 4, 5, 6 (c bonds of the site with J s_i s_j = -1 in the kernel's bit
+// convention: c <= 3 flips outright)
+struct Thr {
+    uint32_t thi4, thi5, thi6;
+    uint64_t T4, T5, T6;
+};
+
+// byte B of v, times 8: the offset of entry v.byte[B] of a table of 8-byte entries (one SDWA op)
+template <int B>
+__device__ __forceinline__ uint32_t byte_x8(uint32_t v)
+{
+    uint32_t r;
+    if constexpr (B == 0)
+        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(v));
+    else if constexpr (B == 1)
+        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(v));
+    else if constexpr (B == 2)
+        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(v));
+    else
+        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(v));
+    return r;
+}
+
+template <int B>
+__device__ __forceinline__ uint2 tab_entry(const uint2* tt, uint32_t idx_bytes)
+{
+    return *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(tt) + byte_x8<B>(idx_bytes));
+}
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8); }
+// bits of a where m is set, of b elsewhere (one v_bfi_b32)
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
+
+// raw | (e << k) as one v_lshl_or_b32; k is a constant after unrolling, and the switch folds to
+// the one asm statement with k as an inline constant
+#define PA_LSHL_OR(K) \
+    case K: asm("v_lshl_or_b32 %0, %1, " #K ", %2" : "=v"(r) : "v"(e), "v"(raw)); break;
+__device__ __forceinline__ uint32_t lshl_or(uint32_t e, int k, uint32_t raw)
+{
+    uint32_t r = raw | (e << k);
+    switch (k) {
+        PA_LSHL_OR(0) PA_LSHL_OR(2) PA_LSHL_OR(4) PA_LSHL_OR(6) PA_LSHL_OR(8) PA_LSHL_OR(10) PA_LSHL_OR(12)
+        PA_LSHL_OR(14)
+        default: break;
+    }
+    return r;
+}
+#undef PA_LSHL_OR
+
+// min(saturated(b - w), 2) per 16-bit half; the min is written out, since as an expression the
+// optimiser may expand it into compares and selects per half
+__device__ __forceinline__ uint32_t first_look(uint32_t b, uint32_t w)
+{
+    typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+    const u16x2 d = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, b), __builtin_bit_cast(u16x2, w));
+    const u16x2 two = {2, 2};
+    uint32_t e;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(e) : "v"(d), "v"(two));
+    return e;
+}
+
+// bit-sliced count of the six bond words: c = c0 + 2 c1 + 4 c2 per bit (two full adders, a half
+// adder and a final full adder)
+__device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4,
+                                           uint32_t b5, uint32_t& c0, uint32_t& c1, uint32_t& c2)
+{
+    const uint32_t s1 = xor3(b0, b1, b2), k1 = maj3(b0, b1, b2);
+    const uint32_t s2 = xor3(b3, b4, b5), k2 = maj3(b3, b4, b5);
+    c0 = s1 ^ s2;
+    const uint32_t k3 = s1 & s2;
+    c1 = xor3(k1, k2, k3);
+    c2 = maj3(k1, k2, k3);
+}
+
+// exact acceptance of the candidate sites (cand: c >= 4) of one word: row i's fields are Philox call
+// call0 + 2 i, site (i, k) has index site0 + 32 i + 2 k.  Thresholds come as scalars: a structure
+// passed by value to this out-of-line call would go through private memory.
+static __device__ __noinline__ uint32_t resolve_word(uint32_t c0, uint32_t c1, uint32_t cand, uint32_t call0,
+                                                     uint32_t site0, uint32_t rr, uint32_t ctr2, uint32_t k0,
+                                                     uint32_t k1, uint32_t thi4, uint32_t thi5, uint32_t thi6,
+                                                     uint64_t T4, uint64_t T5, uint64_t T6)
+{
+    uint32_t racc = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (((cand >> (8 * i)) & 0xFFu) == 0) continue;
+        const uint4v v = philox10(call0 + 2 * i, rr, ctr2, kTagMet, k0, k1);
+        for (int k = 0; k < 8; ++k) {
+            const int b = 8 * i + k;
+            if (!((cand >> b) & 1u)) continue;
+            const uint32_t u = field16(v, k);
+            const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
+            const uint32_t thi = cls == 0 ? thi4 : (cls == 1 ? thi5 : thi6);
+            const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
+            bool a;
+            if (u != thi) a = u < thi;
+            else a = tie_accept(u, T, site0 + 32 * i + 2 * k, rr, ctr2, k0, k1);
+            racc |= (uint32_t)a << b;
+        }
+    }
+    return racc;
+}
+
+// the coupling masks (bit set where J = -1) of every word, by role: 0 the aligned x partner, 1 the
+// rotated one, 2 the aligned y word, 3 the funnel-shifted one, 4 and 5 the z + 1 and z - 1 words.
+// The x partner is the +x bond for sigma = 0 and the -x bond for sigma = 1; the aligned y word is
+// the +y bond for rho = 0 and the -y bond for rho = 1.
+__device__ void build_masks(const int8_t* J, uint32_t* jt, int tid, int nthr)
+{
+    for (int e = tid; e < L * 48; e += nthr) {
+        const int z = e / 48, rem = e % 48, wi = rem / 6, role = rem % 6;
+        const int sg = wi >> 2, rh = (wi >> 1) & 1, h = wi & 1;
+        uint32_t m = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int y = rh + 2 * i + 8 * h;
+            for (int k = 0; k < 8; ++k) {
+                const int x = 2 * k + sg;
+                int sx = x, sy = y, sz = z, dir;
+                // +x: role 0 with sigma = 0, role 1 with sigma = 1; -x the other way round
+                const bool plus_x = (role == 0) == (sg == 0);
+                const bool plus_y = (role == 2) == (rh == 0);
+                if (role <= 1) {
+                    dir = 0;
+                    if (!plus_x) sx = (x + L - 1) % L;
+                } else if (role <= 3) {
+                    dir = 1;
+                    if (!plus_y) sy = (y + L - 1) % L;
+                } else {
+                    dir = 2;
+                    if (role == 5) sz = (z + L - 1) % L;
+                }
+                const int site = sx + L * (sy + L * sz);
+                m |= (uint32_t)(J[3 * site + dir] < 0) << (8 * i + k);
+            }
+        }
+        jt[z * JS + wi * 6 + role] = m;
+    }
+}
+
+// first-look bounds of four sites by their class bits: entry n (low nibble: c0 of sites 0..3, high
+// nibble: c1 of the same sites) holds (bound(site 0) | bound(site 1) << 16, bound(site 2) |
+// bound(site 3) << 16), bound = top + 1 of class c0 + 2 c1 (c = 4, 5, 6; 3 cannot occur at a
+// candidate).  The launch guarantees top <= 0xFFFE.
+__device__ void build_bounds(uint2* tt, const Thr& th, int tid, int nthr)
+{
+    const uint32_t b[4] = {th.thi4 + 1u, th.thi5 + 1u, th.thi6 + 1u, th.thi6 + 1u};
+    for (int n = tid; n < 256; n += nthr) {
+        uint32_t a[4];
+        for (int t = 0; t < 4; ++t) a[t] = ((n >> t) & 1) | (((n >> (4 + t)) & 1) << 1);
+        tt[n] = make_uint2(b[a[0]] | (b[a[1]] << 16), b[a[2]] | (b[a[3]] << 16));
+    }
+}
+
+// the 16 even-x and the 16 odd-x bits of two 16-bit rows (x = row a | row b << 16) as bytes:
+// returns the even bits of row a in byte 0 and of row b in byte 2, odd bits likewise in *odd
+__device__ __forceinline__ uint32_t split_colours(uint32_t x, uint32_t* odd)
+{
+    uint32_t e = x & 0x55555555u, o = (x >> 1) & 0x55555555u;
+    e = (e | (e >> 1)) & 0x33333333u;
+    o = (o | (o >> 1)) & 0x33333333u;
+    e = (e | (e >> 2)) & 0x0F0F0F0Fu;
+    o = (o | (o >> 2)) & 0x0F0F0F0Fu;
+    e = (e | (e >> 4)) & 0x00FF00FFu;
+    o = (o | (o >> 4)) & 0x00FF00FFu;
+    *odd = o;
+    return e;
+}
+
+// inverse: bytes 0 and 2 of e (even x) and of o (odd x) back to two 16-bit rows
+__device__ __forceinline__ uint32_t merge_colours(uint32_t e, uint32_t o)
+{
+    e = (e | (e << 4)) & 0x0F0F0F0Fu;
+    o = (o | (o << 4)) & 0x0F0F0F0Fu;
+    e = (e | (e << 2)) & 0x33333333u;
+    o = (o | (o << 2)) & 0x33333333u;
+    e = (e | (e << 1)) & 0x55555555u;
+    o = (o | (o << 1)) & 0x55555555u;
+    return e | (o << 1);
+}
+
+// The group's rows between HBM (bit-packed: row rho of replica r of group g is the 16-bit word
+// ((g NR + rho) 64 + r) of the spin buffer) and the block's LDS words.  A thread takes four
+// replicas (one 8-byte load per row, so a row of the group is one 128-byte line) and one (z, rho,
+// h) item: four rows, whose even and odd sites become the words W(0, rho, h) and W(1, rho, h).
+// Stores skip the replicas at or past R.
+template <bool STORE>
+__device__ void group_io(const pa_state* st, int64_t g, uint32_t* rows, int64_t R, int tid)
+{
+    uint64_t* G = reinterpret_cast<uint64_t*>((uint8_t*)st->spins[st->cur] + g * (int64_t)NR * 128);
+    const int rq = tid & 15;  // replicas 4 rq .. 4 rq + 3 of the group
+    for (int item = tid >> 4; item < L * 4; item += 16) {
+        const int z = item >> 2, rh = (item >> 1) & 1, h = item & 1;
+        const int row0 = rh + 8 * h + L * z;  // rows row0 + 2 i, i = 0..3
+        uint32_t* W[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int rep = 4 * rq + m;
+            W[m] = rows + (rep >> 4) * ROWW + z * PS + (rh * 2 + h) * RPW + (rep & 15);
+        }
+        if (!STORE) {
+            uint64_t v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = G[(row0 + 2 * i) * 16 + rq];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t r0 = (uint32_t)(v[0] >> (16 * m)) & 0xFFFFu, r1 = (uint32_t)(v[1] >> (16 * m)) & 0xFFFFu;
+                const uint32_t r2 = (uint32_t)(v[2] >> (16 * m)) & 0xFFFFu, r3 = (uint32_t)(v[3] >> (16 * m)) & 0xFFFFu;
+                uint32_t o01, o23;
+                const uint32_t e01 = split_colours(r0 | (r1 << 16), &o01);
+                const uint32_t e23 = split_colours(r2 | (r3 << 16), &o23);
+                // bytes 0 and 2 of the 01 word, then of the 23 word
+                W[m][0] = __builtin_amdgcn_perm(e23, e01, 0x06040200u);
+                W[m][4 * RPW] = __builtin_amdgcn_perm(o23, o01, 0x06040200u);
+            }
+        } else {
+            uint64_t v[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t w0 = W[m][0], w1 = W[m][4 * RPW];
+                // bytes 0, 1 of a word to bytes 0, 2 (rows 0, 1), bytes 2, 3 likewise (rows 2, 3)
+                const uint32_t r01 = merge_colours(__builtin_amdgcn_perm(0u, w0, 0x0C010C00u),
+                                                   __builtin_amdgcn_perm(0u, w1, 0x0C010C00u));
+                const uint32_t r23 = merge_colours(__builtin_amdgcn_perm(0u, w0, 0x0C030C02u),
+                                                   __builtin_amdgcn_perm(0u, w1, 0x0C030C02u));
+                v[0] |= (uint64_t)(r01 & 0xFFFFu) << (16 * m);
+                v[1] |= (uint64_t)(r01 >> 16) << (16 * m);
+                v[2] |= (uint64_t)(r23 & 0xFFFFu) << (16 * m);
+                v[3] |= (uint64_t)(r23 >> 16) << (16 * m);
+            }
+            const int64_t r0 = g * 64 + 4 * rq;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint64_t* a = G + (row0 + 2 * i) * 16 + rq;
+                if (r0 + 3 < R) {
+                    *a = v[i];
+                } else {
+                    uint16_t* a16 = reinterpret_cast<uint16_t*>(a);
+                    for (int m = 0; m < 4; ++m)
+                        if (r0 + m < R) a16[m] = (uint16_t)(v[i] >> (16 * m));
+                }
+            }
+        }
+    }
+}
+
+struct Lane {
+    uint32_t rr, ctr2, k0, k1;
+};
+
+// one colour phase of the two words W(sigma, RHO, h), h = 0, 1, of plane z (rows: the lane's
+// replica column of its wave's rows)
+template <int MODE, int RHO>
+__device__ __forceinline__ void update_words(uint32_t* rows, const uint32_t* jt, const uint2* tt, int z, int sg,
+                                             const Lane& c, const Thr& th)
+{
+    const int zp = (z + 1) & (L - 1), zm = (z + L - 1) & (L - 1);
+    uint32_t* own = rows + z * PS + (sg * 4 + RHO * 2) * RPW;
+    const uint32_t* part = rows + z * PS + ((sg ^ 1) * 4 + RHO * 2) * RPW;
+    const uint32_t* ynb = rows + z * PS + (sg * 4 + (RHO ^ 1) * 2) * RPW;
+    const uint32_t* zpw = rows + zp * PS + (sg * 4 + RHO * 2) * RPW;
+    const uint32_t* zmw = rows + zm * PS + (sg * 4 + RHO * 2) * RPW;
+    const uint32_t* jm = jt + z * JS + (sg * 4 + RHO * 2) * 6;
+    // the rotated x partner: each byte left by one bit (sigma = 0: site x - 1) or right by one
+    // (sigma = 1: site x + 1)
+    const uint32_t mx = sg ? 0x7F7F7F7Fu : 0x01010101u;
+    const int ax = sg ? 1 : 7, bx = sg ? 7 : 1;
+    const uint32_t y0 = ynb[0], y1 = ynb[RPW];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t w = own[h * RPW];
+        const uint32_t p = part[h * RPW];
+        const uint32_t ya = h ? y1 : y0, yo = h ? y0 : y1;
+        // rho = 0: row y - 1 is byte i - 1 of the same-h word, byte 3 of the other for i = 0;
+        // rho = 1: row y + 1 is byte i + 1, byte 0 of the other for i = 3
+        const uint32_t ys = RHO == 0 ? __builtin_amdgcn_alignbit(ya, yo, 24) : __builtin_amdgcn_alignbit(yo, ya, 8);
+        const uint32_t pr = select_bits(mx, p >> ax, p << bx);
+        const uint32_t* J = jm + h * 6;
+        uint32_t c0, c1, c2;
+        bond_count(xor3(w, p, J[0]), xor3(w, pr, J[1]), xor3(w, ya, J[2]), xor3(w, ys, J[3]), xor3(w, zpw[h * RPW], J[4]),
+                   xor3(w, zmw[h * RPW], J[5]), c0, c1, c2);
+        const uint32_t call0 = (uint32_t)(L * z + RHO + 8 * h);  // row i: call0 + 2 i
+        uint32_t nw;
+        bool tie;
+        if constexpr (MODE == 2) {
+            // every top of c >= 4 is zero: candidates reject unless u = 0 (a tie)
+            typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+            u16x2 zmin = {0xFFFF, 0xFFFF};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4v v = philox10(call0 + 2 * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.x), __builtin_bit_cast(u16x2, v.y)));
+                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.z), __builtin_bit_cast(u16x2, v.w)));
+            }
+            tie = zmin.x == 0 || zmin.y == 0;
+            nw = w ^ ~c2;
+        } else {
+            // class bits of sites k = 0..3 (lo) and 4..7 (hi) of row i as byte i: c0 in the low nibble,
+            // c1 in the high one
+            const uint32_t cl = select_bits(0x0F0F0F0Fu, c0, c1 << 4);
+            const uint32_t ch = select_bits(0x0F0F0F0Fu, c0 >> 4, c1);
+            // outcomes: row i's Philox word j (sites 2 j, 2 j + 1) at 2 j + 8 (i & 1) and 16 higher, rows
+            // 0, 1 in ra and rows 2, 3 in rb
+            uint32_t ra = 0, rb = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4v v = philox10(call0 + 2 * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
+                uint2 bl, bh;
+                if (i == 0) { bl = tab_entry<0>(tt, cl); bh = tab_entry<0>(tt, ch); }
+                else if (i == 1) { bl = tab_entry<1>(tt, cl); bh = tab_entry<1>(tt, ch); }
+                else if (i == 2) { bl = tab_entry<2>(tt, cl); bh = tab_entry<2>(tt, ch); }
+                else { bl = tab_entry<3>(tt, cl); bh = tab_entry<3>(tt, ch); }
+                const uint32_t e0 = first_look(bl.x, v.x), e1 = first_look(bl.y, v.y);
+                const uint32_t e2 = first_look(bh.x, v.z), e3 = first_look(bh.y, v.w);
+                const int o = 8 * (i & 1);
+                uint32_t r = i < 2 ? ra : rb;
+                r = (i & 1) ? lshl_or(e0, o, r) : e0;
+                r = lshl_or(e1, o + 2, r);
+                r = lshl_or(e2, o + 4, r);
+                r = lshl_or(e3, o + 6, r);
+                if (i < 2) ra = r;
+                else rb = r;
+            }
+            tie = ((ra | rb) & 0x55555555u) != 0;
+            // accept bits (the high bit of each field) to the sites' bits 8 i + k: rows 0, 1 even k from
+            // ra >> 1, odd k from ra >> 16; rows 2, 3 even k from rb << 15, odd k in place
+            const uint32_t acc = select_bits(0x0000FFFFu, select_bits(0x5555u, ra >> 1, ra >> 16),
+                                             select_bits(0x55550000u, rb << 15, rb));
+            nw = w ^ (~c2 | acc);
+        }
+        if (tie) {
+            const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
+            const uint32_t racc = resolve_word(c0, c1, c2, call0, site0, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5,
+                                               th.thi6, th.T4, th.T5, th.T6);
+            nw = w ^ (~c2 | racc);
+        }
+        own[h * RPW] = nw;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_sweep16c(const pa_state* __restrict__ st, SweepParams p, Thr th)
+{
+    __shared__ uint32_t s_rows[WPB * ROWW];
+    __shared__ uint32_t s_jt[L * JS];
+    __shared__ uint2 s_tt[256];
+    if (st->status) return;  // sticky error: the population stays as it is
+    const int64_t R = st->R;
+    const int64_t g = blockIdx.x;
+    if (g * 64 >= R) return;  // the whole block is past the population
+    const int tid = threadIdx.x;
+    build_masks(st->J, s_jt, tid, 256);
+    if (MODE != 2) build_bounds(s_tt, th, tid, 256);
+    group_io<false>(st, g, s_rows, R, tid);
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int q = lane & (RPW - 1), j = lane >> 4;
+    uint32_t* rows = s_rows + wave * ROWW + q;
+    Lane c;
+    c.rr = (uint32_t)(g * 64 + wave * RPW + q);
+    c.k0 = (uint32_t)st->seed;
+    c.k1 = (uint32_t)(st->seed >> 32);
+    for (int s = 0; s < p.n_sweeps; ++s) {
+        for (int col = 0; col < 2; ++col) {
+            c.ctr2 = (uint32_t)(2 * (p.t0 + s) + col);
+            for (int t = 0; t < 4; ++t) {
+                const int z = 4 * j + t;
+                // words of colour col: sigma + rho = col + z (mod 2), and z = t (mod 2) over the wave
+                const int sg0 = (col + t) & 1;
+                update_words<MODE, 0>(rows, s_jt, s_tt, z, sg0, c, th);
+                update_words<MODE, 1>(rows, s_jt, s_tt, z, sg0 ^ 1, c, th);
+            }
+            // the other colour reads these words next (other lanes of the replica too)
+            wave_sync();
+        }
+    }
+
+    // energy of the final configuration: E = n_bonds - 2 (bonds whose word bit is set), counting
+    // each site's +x, +y and +z bonds
+    int neg = 0;
+    for (int t = 0; t < 4; ++t) {
+        const int z = 4 * j + t, zp = (z + 1) & (L - 1);
+#pragma unroll
+        for (int wi = 0; wi < 8; ++wi) {
+            const int sg = wi >> 2, rh = (wi >> 1) & 1, h = wi & 1;
+            const uint32_t w = rows[z * PS + wi * RPW];
+            const uint32_t p = rows[z * PS + (wi ^ 4) * RPW];
+            const uint32_t ya = rows[z * PS + (wi ^ 2) * RPW];
+            const uint32_t yo = rows[z * PS + (wi ^ 3) * RPW];
+            const uint32_t* J = s_jt + z * JS + wi * 6;
+            // +x: the partner itself (sigma = 0) or its bytes rotated right (sigma = 1)
+            const uint32_t px = sg ? (((p >> 1) & 0x7F7F7F7Fu) | ((p << 7) & 0x80808080u)) : p;
+            // +y: the aligned word (rho = 0) or the funnel of the pair (rho = 1)
+            const uint32_t py = rh ? __builtin_amdgcn_alignbit(yo, ya, 8) : ya;
+            (void)h;
+            neg += __popc(xor3(w, px, J[sg ? 1 : 0]));
+            neg += __popc(xor3(w, py, J[rh ? 3 : 2]));
+            neg += __popc(xor3(w, rows[zp * PS + wi * RPW], J[4]));
+        }
+    }
+    for (int off = RPW; off < 64; off <<= 1) neg += __shfl_xor(neg, off, 64);
+    const int64_t r = g * 64 + wave * RPW + q;
+    if (j == 0 && r < R) st->energy[st->cur][r] = st->n_bonds - 2 * neg;
+    __syncthreads();
+    group_io<true>(st, g, s_rows, R, tid);
+}
+
+}  // namespace colour
+
+// the colour-packed sweep of an L = 16 cube in the bit-packed layout; PA_ERR_ARG when the run or
+// the thresholds are not ones it handles (tops above 0xFFFE leave no room for the + 1 of the bound)
+int launch_sweep_colour(const pa_run& run, const SweepParams& p, hipStream_t s)
+{
+    if (run.dim != 3 || run.L != colour::L || run.layout != PA_BITS64 || !fast_sweep_thresholds_ok(p))
+        return PA_ERR_ARG;
+    colour::Thr th;
+    th.thi4 = p.thi[4];
+    th.thi5 = p.thi[5];
+    th.thi6 = p.thi[6];
+    th.T4 = p.T64[4];
+    th.T5 = p.T64[5];
+    th.T6 = p.T64[6];
+    const int64_t blocks = (run.capacity + 63) / 64;
+    if (blocks <= 0) return PA_OK;
+    if (th.thi4 == 0 && th.thi5 == 0 && th.thi6 == 0)
+        hipLaunchKernelGGL(colour::k_sweep16c<2>, dim3((unsigned)blocks), dim3(256), 0, s, run.state, p, th);
+    else
+        hipLaunchKernelGGL(colour::k_sweep16c<0>, dim3((unsigned)blocks), dim3(256), 0, s, run.state, p, th);
+    return PA_OK;
+}
+
+}  // namespace pa

@@ -184,17 +184,43 @@ typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 // bits of a where m is set, of b elsewhere (one v_bfi_b32)
 __device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
 
+// three-input xor and majority, one v_bitop3_b32 each (truth tables over a = 0xF0, b = 0xCC, c = 0xAA);
+// written as builtins so that the optimiser cannot re-split the adder tree into two-input ops
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8); }
+
 // bit-sliced count of the six bond words: c = c0 + 2 c1 + 4 c2 bonds with J s_i s_j = -1 per bit
+// (two full adders, a half adder and a final full adder: eight ops)
 __device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4,
                                            uint32_t b5, uint32_t& c0, uint32_t& c1, uint32_t& c2)
 {
-    const uint32_t s1 = b0 ^ b1 ^ b2, k1c = (b0 & b1) | (b2 & (b0 ^ b1));
-    const uint32_t s2 = b3 ^ b4 ^ b5, k2c = (b3 & b4) | (b5 & (b3 ^ b4));
+    const uint32_t s1 = xor3(b0, b1, b2), k1c = maj3(b0, b1, b2);
+    const uint32_t s2 = xor3(b3, b4, b5), k2c = maj3(b3, b4, b5);
     c0 = s1 ^ s2;
     const uint32_t k3c = s1 & s2;
-    c1 = k1c ^ k2c ^ k3c;
-    c2 = (k1c & k2c) | (k3c & (k1c ^ k2c));
+    c1 = xor3(k1c, k2c, k3c);
+    c2 = maj3(k1c, k2c, k3c);
 }
+
+// raw | (e << k) as one v_lshl_or_b32 (left to itself the compiler pairs shifts into v_or3_b32,
+// one and a half ops per field instead of one).  k must be a constant after unrolling: the switch
+// then folds to the one asm statement with k as an inline constant.
+#define PA_LSHL_OR(K) \
+    case K: asm("v_lshl_or_b32 %0, %1, " #K ", %2" : "=v"(r) : "v"(e), "v"(raw)); break;
+__device__ __forceinline__ uint32_t lshl_or(uint32_t e, int k, uint32_t raw)
+{
+    uint32_t r = raw | (e << k);
+    switch (k) {
+        PA_LSHL_OR(0) PA_LSHL_OR(1) PA_LSHL_OR(2) PA_LSHL_OR(3) PA_LSHL_OR(4) PA_LSHL_OR(5) PA_LSHL_OR(6)
+        PA_LSHL_OR(7) PA_LSHL_OR(8) PA_LSHL_OR(9) PA_LSHL_OR(10) PA_LSHL_OR(11) PA_LSHL_OR(12) PA_LSHL_OR(13)
+        PA_LSHL_OR(14) PA_LSHL_OR(15) PA_LSHL_OR(16) PA_LSHL_OR(17) PA_LSHL_OR(18) PA_LSHL_OR(19) PA_LSHL_OR(20)
+        PA_LSHL_OR(21) PA_LSHL_OR(22) PA_LSHL_OR(23) PA_LSHL_OR(24) PA_LSHL_OR(25) PA_LSHL_OR(26) PA_LSHL_OR(27)
+        PA_LSHL_OR(28) PA_LSHL_OR(29) PA_LSHL_OR(30) PA_LSHL_OR(31)
+        default: break;
+    }
+    return r;
+}
+#undef PA_LSHL_OR
 
 // one colour of one plane z of this lane's replica: rows y and y + L/2 (not neighbours for L >= 6,
 // nor for L = 4) sit in the low and high half of one 32-bit word, so one bit-sliced count serves
@@ -238,11 +264,11 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
         const uint32_t zmv = Pm[yy * RPW];
         const uint32_t* jr = JT + yy * 8;
         // x + 1 and x - 1 neighbours, periodic within each half
-        const uint32_t rp = ((own >> 1) & XP) | ((own << (L - 1)) & ~XP);
-        const uint32_t rm = ((own << 1) & XM) | ((own >> (L - 1)) & ~XM);
+        const uint32_t rp = select_bits(XP, own >> 1, own << (L - 1));
+        const uint32_t rm = select_bits(XM, own << 1, own >> (L - 1));
         uint32_t c0, c1, c2;
-        bond_count(own ^ rp ^ jr[0], own ^ yp ^ jr[1], own ^ zpv ^ jr[2], own ^ rm ^ jr[3], own ^ ym ^ jr[4],
-                   own ^ zmv ^ jr[5], c0, c1, c2);
+        bond_count(xor3(own, rp, jr[0]), xor3(own, yp, jr[1]), xor3(own, zpv, jr[2]), xor3(own, rm, jr[3]),
+                   xor3(own, ym, jr[4]), xor3(own, zmv, jr[5]), c0, c1, c2);
         const uint32_t colmask = (yy & 1) ? cmB : cmA;
         const int par = p0 ^ (yy & 1);
         uint32_t flip;
@@ -297,8 +323,8 @@ __device__ __forceinline__ void plane_update_pairs(uint32_t* rows32, const uint3
                     uint32_t eA, eB;
                     asm("v_pk_min_u16 %0, %1, %2" : "=v"(eA) : "v"(dA), "v"(two));
                     asm("v_pk_min_u16 %0, %1, %2" : "=v"(eB) : "v"(dB), "v"(two));
-                    raw |= eA << (2 * m);
-                    raw |= eB << (2 * m + 2);
+                    raw = lshl_or(eA, 2 * m, raw);
+                    raw = lshl_or(eB, 2 * m + 2, raw);
                     // MODE 1: classes 5 and 6 have top 0, so u == 0 is a tie there
                     if (MODE == 1) zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(wA, wB));
                 }

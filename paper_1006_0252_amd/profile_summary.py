@@ -21,9 +21,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_fast.hip", "paper_1006_0252_amd/csrc/pa_sweep_util.h",
-                 "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
-SWEEP_KERNEL = "k_sweep3f<16"
+SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_colour.hip", "paper_1006_0252_amd/csrc/pa_sweep.hip",
+                 "paper_1006_0252_amd/csrc/pa_sweep_util.h", "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
+SWEEP_KERNEL = "k_sweep16c"
+KERNEL_LABEL = "k_sweep16c (colour-packed words, bit-packed L=16; pa_sweep, 10 sweeps per launch)"
 ATTEMPTS_PER_LAUNCH = 1_000_000 * 4096 * 10  # profile_sweep.py: R0 = 1e6 replicas, L = 16, 10 sweeps
 INSTRUCTION_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VALU_INT32",
                         "SQ_INSTS_VALU_INT64", "SQ_INSTS_SMEM", "SQ_INSTS_BRANCH")
@@ -72,7 +73,7 @@ def counters(dirs, out):
             regimes.setdefault(str(reg), {}).update(c)
     per_attempt = {r: {k: v * 64 / ATTEMPTS_PER_LAUNCH for k, v in c.items() if k in INSTRUCTION_COUNTERS}
                    for r, c in regimes.items()}
-    res = {"kernel": "k_sweep3f<16, bits64> (pa_sweep, 10 sweeps per launch)",
+    res = {"kernel": KERNEL_LABEL,
            "workload": "cube L=16, R0=1e6, bit-packed; one launch each at beta = 0.5, 2, 4 (first-look regimes 0, 1, 2)",
            "attempts_per_launch": ATTEMPTS_PER_LAUNCH, "counters": regimes, "per_attempt": per_attempt,
            "valu_per_attempt": {r: v["SQ_INSTS_VALU"] for r, v in per_attempt.items() if "SQ_INSTS_VALU" in v},
@@ -99,7 +100,7 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out, copy_byte
     copy_f = max(c.get("FETCH_SIZE", 0.0) for c in cf.values())
     copy_w = max(c.get("WRITE_SIZE", 0.0) for c in cw.values())
     fs, ws = copy_bytes / (copy_f * 1024), copy_bytes / (copy_w * 1024)
-    res = {"kernel": "k_sweep3f<16, bits64> (pa_sweep, 10 sweeps per launch)",
+    res = {"kernel": KERNEL_LABEL,
            "workload": "cube L=16, R0=1e6, bit-packed, the first steps of the 301-temperature schedule",
            "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
            "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes, "fetch_kib_read": copy_f,

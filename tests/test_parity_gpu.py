@@ -112,7 +112,8 @@ def test_sweep_launch_shapes_agree(L, layout, cap):
     so, Eo = o.init_population(3, L, J, 7, R0)
     o.sweep(3, L, J, 7, 0.8, R0, so, Eo, 0, 3)
     try:
-        for lpr, wpb in ((1, 1), (1, 4), (2, 2), (2, 4), (4, 1), (4, 3), (4, 4)):
+        # (0, 0): the default, for the bit-packed L = 16 cube the colour-packed kernel
+        for lpr, wpb in ((0, 0), (1, 1), (1, 4), (2, 2), (2, 4), (4, 1), (4, 3), (4, 4)):
             note(f"sweep shape L={L} {layout} lpr={lpr} wpb={wpb}")
             pa.set_sweep_config(lpr, wpb)
             run = make_run(3, L, R0, layout, capacity=cap)
@@ -122,6 +123,29 @@ def test_sweep_launch_shapes_agree(L, layout, cap):
             assert np.array_equal(s, so) and np.array_equal(E, Eo), f"lpr={lpr} wpb={wpb}"
     finally:
         pa.set_sweep_config(0, 0)
+
+
+@pytest.mark.parametrize("beta", [0.05, 0.5, 1.2, 1.5, 2.5, 3.0, 6.0])
+def test_colour_kernel_matches_row_pair_kernel(beta):
+    # the default sweep of the bit-packed L = 16 cube (words of one colour) against the row-pair
+    # kernel (taken when a launch shape is forced), over 20000 replicas in 313 groups, the last one
+    # partial: the same sample bit for bit, in every first-look regime
+    R0 = 20_000
+    note(f"colour vs row-pair kernel beta={beta}")
+    out = []
+    try:
+        for cfg in ((0, 0), (4, 4)):
+            pa.set_sweep_config(*cfg)
+            run = make_run(3, 16, R0, "bits64", seed=11, dseed=2)
+            sched = pa.Schedule([0.0, beta], 4, run.n_bins, device=DEV)
+            step = sched.step(1)
+            step.t0 = 17
+            run.sweep(step)
+            out.append(run.population())
+    finally:
+        pa.set_sweep_config(0, 0)
+    (s0, E0), (s1, E1) = out
+    assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
 
 
 RESAMPLE_CASES = [(1, 64, "u8", 300), (1, 64, "bits64", 300), (3, 4, "bits64", 500), (3, 6, "u8", 400),
