@@ -75,8 +75,12 @@ __device__ __forceinline__ uint2 tab_entry(const uint2* tt, uint32_t idx_bytes)
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8); }
-// bits of a where m is set, of b elsewhere (one v_bfi_b32)
-__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
+// bits of a where m is set, of b elsewhere: one v_bitop3_b32 (m ? a : b is truth table 0xCA), also
+// when m is not a constant (the optimiser would spend a second op on ~m)
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
+}
 
 // raw | (e << k) as one v_lshl_or_b32; k is a constant after unrolling, and the switch folds to
 // the one asm statement with k as an inline constant
@@ -119,82 +123,58 @@ __device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2
     c2 = maj3(k1, k2, k3);
 }
 
-// exact acceptance of the candidate sites (cand: c >= 4) of one word: row i's fields are Philox call
-// call0 + 2 i, site (i, k) has index site0 + 32 i + 2 k.  Thresholds come as scalars: a structure
-// passed by value to this out-of-line call would go through private memory.
-static __device__ __noinline__ uint32_t resolve_word(uint32_t c0, uint32_t c1, uint32_t cand, uint32_t call0,
-                                                     uint32_t site0, uint32_t rr, uint32_t ctr2, uint32_t k0,
-                                                     uint32_t k1, uint32_t thi4, uint32_t thi5, uint32_t thi6,
-                                                     uint64_t T4, uint64_t T5, uint64_t T6)
+// Exact decisions of first-look ties (Sec. II: the 16-bit field u is the top of a 64-bit uniform;
+// when it equals the top of the threshold, the 48 low bits decide).  A wave takes these paths when
+// any of its lanes has a tie, so they touch only the tied sites.
+//
+// General thresholds: bits = candidate sites whose field equals the top of their class, so u is
+// that top and only the low bits need drawing.  Returns the accepted ones.  Thresholds come as
+// scalars: a structure passed by value to this out-of-line call would go through private memory.
+static __device__ __noinline__ uint32_t resolve_ties(uint32_t bits, uint32_t c0, uint32_t c1, uint32_t site0,
+                                                     uint32_t rr, uint32_t ctr2, uint32_t k0, uint32_t k1,
+                                                     uint32_t thi4, uint32_t thi5, uint32_t thi6, uint64_t T4,
+                                                     uint64_t T5, uint64_t T6)
 {
     uint32_t racc = 0;
-    for (int i = 0; i < 4; ++i) {
-        if (((cand >> (8 * i)) & 0xFFu) == 0) continue;
-        const uint4v v = philox10(call0 + 2 * i, rr, ctr2, kTagMet, k0, k1);
-        for (int k = 0; k < 8; ++k) {
-            const int b = 8 * i + k;
-            if (!((cand >> b) & 1u)) continue;
-            const uint32_t u = field16(v, k);
-            const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
-            const uint32_t thi = cls == 0 ? thi4 : (cls == 1 ? thi5 : thi6);
-            const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
-            bool a;
-            if (u != thi) a = u < thi;
-            else a = tie_accept(u, T, site0 + 32 * i + 2 * k, rr, ctr2, k0, k1);
-            racc |= (uint32_t)a << b;
-        }
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
+        const uint32_t u = cls == 0 ? thi4 : (cls == 1 ? thi5 : thi6);
+        const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
+        // site (i, k) of the word: bit 8 i + k, index site0 + 32 i + 2 k
+        const uint32_t site = site0 + 32u * (uint32_t)(b >> 3) + 2u * (uint32_t)(b & 7);
+        racc |= (uint32_t)tie_accept(u, T, site, rr, ctr2, k0, k1) << b;
     }
     return racc;
 }
 
-// the coupling masks (bit set where J = -1) of every word, by role: 0 the aligned x partner, 1 the
-// rotated one, 2 the aligned y word, 3 the funnel-shifted one, 4 and 5 the z + 1 and z - 1 words.
-// The x partner is the +x bond for sigma = 0 and the -x bond for sigma = 1; the aligned y word is
-// the +y bond for rho = 0 and the -y bond for rho = 1.
-__device__ void build_masks(const int8_t* J, uint32_t* jt, int tid, int nthr)
+// Every top zero: a candidate accepts only if u = 0 and its low bits fall below the threshold.
+// rows: the rows (bit i) whose fields hold a zero; their Philox calls are drawn again.
+static __device__ __noinline__ uint32_t resolve_zero_rows(uint32_t rows, uint32_t cand, uint32_t c0, uint32_t c1,
+                                                          uint32_t call0, uint32_t site0, uint32_t rr, uint32_t ctr2,
+                                                          uint32_t k0, uint32_t k1, uint64_t T4, uint64_t T5,
+                                                          uint64_t T6)
 {
-    for (int e = tid; e < L * 48; e += nthr) {
-        const int z = e / 48, rem = e % 48, wi = rem / 6, role = rem % 6;
-        const int sg = wi >> 2, rh = (wi >> 1) & 1, h = wi & 1;
-        uint32_t m = 0;
-        for (int i = 0; i < 4; ++i) {
-            const int y = rh + 2 * i + 8 * h;
-            for (int k = 0; k < 8; ++k) {
-                const int x = 2 * k + sg;
-                int sx = x, sy = y, sz = z, dir;
-                // +x: role 0 with sigma = 0, role 1 with sigma = 1; -x the other way round
-                const bool plus_x = (role == 0) == (sg == 0);
-                const bool plus_y = (role == 2) == (rh == 0);
-                if (role <= 1) {
-                    dir = 0;
-                    if (!plus_x) sx = (x + L - 1) % L;
-                } else if (role <= 3) {
-                    dir = 1;
-                    if (!plus_y) sy = (y + L - 1) % L;
-                } else {
-                    dir = 2;
-                    if (role == 5) sz = (z + L - 1) % L;
-                }
-                const int site = sx + L * (sy + L * sz);
-                m |= (uint32_t)(J[3 * site + dir] < 0) << (8 * i + k);
-            }
-        }
-        jt[z * JS + wi * 6 + role] = m;
+    uint32_t bits = 0;
+    while (rows) {
+        const int i = __builtin_ctz(rows);
+        rows &= rows - 1u;
+        const uint4v v = philox10(call0 + 2u * (uint32_t)i, rr, ctr2, kTagMet, k0, k1);
+        for (int k = 0; k < 8; ++k)
+            if (field16(v, k) == 0) bits |= 1u << (8 * i + k);
     }
-}
-
-// first-look bounds of four sites by their class bits: entry n (low nibble: c0 of sites 0..3, high
-// nibble: c1 of the same sites) holds (bound(site 0) | bound(site 1) << 16, bound(site 2) |
-// bound(site 3) << 16), bound = top + 1 of class c0 + 2 c1 (c = 4, 5, 6; 3 cannot occur at a
-// candidate).  The launch guarantees top <= 0xFFFE.
-__device__ void build_bounds(uint2* tt, const Thr& th, int tid, int nthr)
-{
-    const uint32_t b[4] = {th.thi4 + 1u, th.thi5 + 1u, th.thi6 + 1u, th.thi6 + 1u};
-    for (int n = tid; n < 256; n += nthr) {
-        uint32_t a[4];
-        for (int t = 0; t < 4; ++t) a[t] = ((n >> t) & 1) | (((n >> (4 + t)) & 1) << 1);
-        tt[n] = make_uint2(b[a[0]] | (b[a[1]] << 16), b[a[2]] | (b[a[3]] << 16));
+    bits &= cand;
+    uint32_t racc = 0;
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
+        const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
+        const uint32_t site = site0 + 32u * (uint32_t)(b >> 3) + 2u * (uint32_t)(b & 7);
+        racc |= (uint32_t)tie_accept(0u, T, site, rr, ctr2, k0, k1) << b;
     }
+    return racc;
 }
 
 // the 16 even-x and the 16 odd-x bits of two 16-bit rows (x = row a | row b << 16) as bytes:
@@ -210,6 +190,66 @@ __device__ __forceinline__ uint32_t split_colours(uint32_t x, uint32_t* odd)
     o = (o | (o >> 4)) & 0x00FF00FFu;
     *odd = o;
     return e;
+}
+
+// The coupling masks (bit set where J = -1) of every word, by role: 0 the aligned x partner, 1 the
+// rotated one, 2 the aligned y word, 3 the funnel-shifted one, 4 and 5 the z + 1 and z - 1 words.
+// The x partner is the +x bond for sigma = 0 and the -x bond for sigma = 1; the aligned y word is
+// the +y bond for rho = 0 and the -y bond for rho = 1.  Thread t (of 256) takes lattice row t
+// (y = t mod 16, z = t / 16): the six bond masks of its 16 sites (the -y and -z bonds are the +y
+// bonds of row y - 1 and the +z bonds of plane z - 1), split into even-x and odd-x bytes, become
+// byte (y >> 1) & 3 of the masks of the words W(sigma, y & 1, y >> 3) of plane z.
+__device__ void build_masks(const int8_t* J, uint32_t* jt, int tid)
+{
+    const int y = tid & (L - 1), z = tid >> 4;
+    const int8_t* a = J + 3 * L * (y + L * z);
+    const int8_t* b = J + 3 * L * (((y + L - 1) & (L - 1)) + L * z);
+    const int8_t* c = J + 3 * L * (y + L * ((z + L - 1) & (L - 1)));
+    uint32_t px = 0, py = 0, pz = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int x = 0; x < L; ++x) {
+        px |= (uint32_t)(a[3 * x + 0] < 0) << x;
+        py |= (uint32_t)(a[3 * x + 1] < 0) << x;
+        pz |= (uint32_t)(a[3 * x + 2] < 0) << x;
+        my |= (uint32_t)(b[3 * x + 1] < 0) << x;
+        mz |= (uint32_t)(c[3 * x + 2] < 0) << x;
+    }
+    const uint32_t mx = ((px << 1) | (px >> (L - 1))) & 0xFFFFu;  // the -x bond of x is the +x bond of x - 1
+    const int rh = y & 1, i = (y >> 1) & 3, h = y >> 3;
+    // roles for sigma = 0: +x, -x, then (rho = 0) +y, -y or (rho = 1) -y, +y, then +z, -z
+    uint32_t o_x, o_y, o_z;
+    const uint32_t e_x = split_colours(px | (mx << 16), &o_x);
+    const uint32_t e_y = split_colours((rh ? my : py) | ((rh ? py : my) << 16), &o_y);
+    const uint32_t e_z = split_colours(pz | (mz << 16), &o_z);
+    uint8_t* jb = reinterpret_cast<uint8_t*>(jt);
+    uint8_t* w0 = jb + 4 * (z * JS + (rh * 2 + h) * 6) + i;  // sigma = 0
+    uint8_t* w1 = w0 + 4 * 4 * 6;                             // sigma = 1
+    w0[0] = (uint8_t)e_x;          // even x: aligned partner +x, rotated -x
+    w0[4] = (uint8_t)(e_x >> 16);
+    w1[0] = (uint8_t)(o_x >> 16);  // odd x: aligned partner -x, rotated +x
+    w1[4] = (uint8_t)o_x;
+    w0[8] = (uint8_t)e_y;
+    w0[12] = (uint8_t)(e_y >> 16);
+    w1[8] = (uint8_t)o_y;
+    w1[12] = (uint8_t)(o_y >> 16);
+    w0[16] = (uint8_t)e_z;
+    w0[20] = (uint8_t)(e_z >> 16);
+    w1[16] = (uint8_t)o_z;
+    w1[20] = (uint8_t)(o_z >> 16);
+}
+
+// first-look bounds of four sites by their class bits: entry n (low nibble: c0 of sites 0..3, high
+// nibble: c1 of the same sites) holds (bound(site 0) | bound(site 1) << 16, bound(site 2) |
+// bound(site 3) << 16), bound = top + 1 of class c0 + 2 c1 (c = 4, 5, 6; 3 cannot occur at a
+// candidate).  The launch guarantees top <= 0xFFFE.
+__device__ void build_bounds(uint2* tt, const Thr& th, int tid, int nthr)
+{
+    const uint32_t b[4] = {th.thi4 + 1u, th.thi5 + 1u, th.thi6 + 1u, th.thi6 + 1u};
+    for (int n = tid; n < 256; n += nthr) {
+        uint32_t a[4];
+        for (int t = 0; t < 4; ++t) a[t] = ((n >> t) & 1) | (((n >> (4 + t)) & 1) << 1);
+        tt[n] = make_uint2(b[a[0]] | (b[a[1]] << 16), b[a[2]] | (b[a[3]] << 16));
+    }
 }
 
 // inverse: bytes 0 and 2 of e (even x) and of o (odd x) back to two 16-bit rows
@@ -326,19 +366,29 @@ __device__ __forceinline__ void update_words(uint32_t* rows, const uint32_t* jt,
                    xor3(w, zmw[h * RPW], J[5]), c0, c1, c2);
         const uint32_t call0 = (uint32_t)(L * z + RHO + 8 * h);  // row i: call0 + 2 i
         uint32_t nw;
-        bool tie;
         if constexpr (MODE == 2) {
-            // every top of c >= 4 is zero: candidates reject unless u = 0 (a tie)
+            // every top of c >= 4 is zero: candidates reject unless u = 0 (a tie).  The minimum field
+            // of each row, then of the word
             typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
-            u16x2 zmin = {0xFFFF, 0xFFFF};
+            u16x2 m[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const uint4v v = philox10(call0 + 2 * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.x), __builtin_bit_cast(u16x2, v.y)));
-                zmin = __builtin_elementwise_min(zmin, __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.z), __builtin_bit_cast(u16x2, v.w)));
+                m[i] = __builtin_elementwise_min(
+                    __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.x), __builtin_bit_cast(u16x2, v.y)),
+                    __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.z), __builtin_bit_cast(u16x2, v.w)));
             }
-            tie = zmin.x == 0 || zmin.y == 0;
+            const u16x2 zmin = __builtin_elementwise_min(__builtin_elementwise_min(m[0], m[1]),
+                                                         __builtin_elementwise_min(m[2], m[3]));
             nw = w ^ ~c2;
+            if (zmin.x == 0 || zmin.y == 0) {
+                uint32_t rows = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rows |= (uint32_t)(m[i].x == 0 || m[i].y == 0) << i;
+                const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
+                nw = w ^ (~c2 | resolve_zero_rows(rows, c2, c0, c1, call0, site0, c.rr, c.ctr2, c.k0, c.k1, th.T4,
+                                                  th.T5, th.T6));
+            }
         } else {
             // class bits of sites k = 0..3 (lo) and 4..7 (hi) of row i as byte i: c0 in the low nibble,
             // c1 in the high one
@@ -366,18 +416,22 @@ __device__ __forceinline__ void update_words(uint32_t* rows, const uint32_t* jt,
                 if (i < 2) ra = r;
                 else rb = r;
             }
-            tie = ((ra | rb) & 0x55555555u) != 0;
             // accept bits (the high bit of each field) to the sites' bits 8 i + k: rows 0, 1 even k from
             // ra >> 1, odd k from ra >> 16; rows 2, 3 even k from rb << 15, odd k in place
-            const uint32_t acc = select_bits(0x0000FFFFu, select_bits(0x5555u, ra >> 1, ra >> 16),
-                                             select_bits(0x55550000u, rb << 15, rb));
+            uint32_t acc = select_bits(0x0000FFFFu, select_bits(0x5555u, ra >> 1, ra >> 16),
+                                       select_bits(0x55550000u, rb << 15, rb));
+            if (((ra | rb) & 0x55555555u) != 0) {
+                // tie bits (the low bit of each field) to the sites' bits likewise: ra's even k in place,
+                // odd k from ra >> 15; rb's even k from rb << 16, odd k from rb << 1
+                const uint32_t ties = select_bits(0x0000FFFFu, select_bits(0x5555u, ra, ra >> 15),
+                                                  select_bits(0x55550000u, rb << 16, rb << 1)) & c2;
+                if (ties) {
+                    const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
+                    acc |= resolve_ties(ties, c0, c1, site0, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5, th.thi6,
+                                        th.T4, th.T5, th.T6);
+                }
+            }
             nw = w ^ (~c2 | acc);
-        }
-        if (tie) {
-            const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
-            const uint32_t racc = resolve_word(c0, c1, c2, call0, site0, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5,
-                                               th.thi6, th.T4, th.T5, th.T6);
-            nw = w ^ (~c2 | racc);
         }
         own[h * RPW] = nw;
     }
@@ -394,7 +448,7 @@ __global__ void __launch_bounds__(256) k_sweep16c(const pa_state* __restrict__ s
     const int64_t g = blockIdx.x;
     if (g * 64 >= R) return;  // the whole block is past the population
     const int tid = threadIdx.x;
-    build_masks(st->J, s_jt, tid, 256);
+    build_masks(st->J, s_jt, tid);
     if (MODE != 2) build_bounds(s_tt, th, tid, 256);
     group_io<false>(st, g, s_rows, R, tid);
     __syncthreads();
