@@ -26,6 +26,9 @@ SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_colour.hip", "paper_1006_025
 SWEEP_KERNEL = "k_sweep16c"
 KERNEL_LABEL = "k_sweep16c (colour-packed words, bit-packed L=16; pa_sweep, 10 sweeps per launch)"
 ATTEMPTS_PER_LAUNCH = 1_000_000 * 4096 * 10  # profile_sweep.py: R0 = 1e6 replicas, L = 16, 10 sweeps
+# HBM bytes a sweep launch of 1e6 L = 16 replicas must move: each replica's 4096 spin bits read and
+# written once (512 + 512 bytes) and its 4-byte energy written
+ALGORITHMIC_BYTES_PER_LAUNCH = 1_000_000 * (512 + 512 + 4)
 INSTRUCTION_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VALU_INT32",
                         "SQ_INSTS_VALU_INT64", "SQ_INSTS_SMEM", "SQ_INSTS_BRANCH")
 
@@ -106,6 +109,7 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out, copy_byte
            "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes, "fetch_kib_read": copy_f,
                                 "write_kib_read": copy_w, "fetch_scale": fs, "write_scale": ws},
            "bytes_per_launch": f_kib * 1024 * fs + w_kib * 1024 * ws,
+           "algorithmic_bytes_per_launch": ALGORITHMIC_BYTES_PER_LAUNCH,
            "source_digest": sweep_source_digest()}
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
