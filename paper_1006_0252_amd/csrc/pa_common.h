@@ -105,6 +105,30 @@ struct SweepParams {
     int32_t rpb;         // replicas (u8) or 64-replica groups (bits64) per block
 };
 
+// a batched sweep's run order: position p of the work list holds run order.run[p] (at most
+// kMaxBatch runs)
+constexpr int kMaxBatch = 1024;
+struct BatchOrder {
+    uint16_t run[kMaxBatch];
+};
+
+// lanes per replica of the row-pair batch kernel for each lattice size (L = 2 mod 4 needs one lane
+// per replica so that the Philox phase of a plane is uniform over the wave)
+__host__ __device__ constexpr int batch_lpr(int L) { return L % 4 != 0 ? 1 : (L >= 12 ? 4 : (L >= 8 ? 2 : 1)); }
+
+// the colour-string kernel: bit-packed cubes of L = 4, 6, 8, 10, one lane per replica
+__host__ __device__ inline bool string_sweep_supported(int dim, int L, int layout)
+{
+    return dim == 3 && layout == PA_BITS64 && (L == 4 || L == 6 || L == 8 || L == 10);
+}
+
+// replicas per work item of a batched cube sweep: one 64-replica group for the colour-string
+// kernel, 64 / lanes per replica for the row-pair kernel
+__host__ __device__ inline int batch_tile_replicas(int L, int layout)
+{
+    return string_sweep_supported(3, L, layout) ? 64 : 64 / batch_lpr(L);
+}
+
 // host launch helpers (defined in the .hip files)
 int launch_init(const pa_run& run, const int8_t* J_host, hipStream_t s);
 int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s);
@@ -113,6 +137,11 @@ int launch_sweep_chain_batch(const pa_run* runs, int n, const pa_step& step, hip
 int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb, hipStream_t s);
 // the colour-packed kernel of the bit-packed L = 16 cube (PA_ERR_ARG for any other run)
 int launch_sweep_colour(const pa_run& run, const SweepParams& p, hipStream_t s);
+// the colour-string kernel (string_sweep_supported runs): one run, or one group of equal-L runs of a
+// batch (persistent waves taking items, or one item per block)
+int launch_sweep_strings(const pa_run& run, const SweepParams& p, hipStream_t s);
+int launch_sweep_strings_group(int L, pa_state* base, int pos0, int pos1, const BatchOrder& order,
+                               const SweepParams& p, bool persistent, int64_t grid, hipStream_t s);
 // batched launchers: n runs whose device states are contiguous (runs[r].state == runs[0].state + r)
 int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
 int launch_hist(const pa_run* runs, int n, hipStream_t s);

@@ -528,9 +528,12 @@ int launch_sweep(const pa_run& run, const pa_step& step, hipStream_t s)
     if (g_override.lpr) cfg = g_override;
     int st;
     if (fast_sweep_supported(run.dim, run.L) && fast_sweep_thresholds_ok(p)) {
-        // the bit-packed L = 16 cube takes the colour-packed kernel unless a launch shape is forced
+        // bit-packed cubes take the colour-packed kernel (L = 16) or the colour-string kernel (L = 4,
+        // 6, 8, 10) unless a launch shape is forced
         if (!g_override.lpr && run.L == 16 && run.layout == PA_BITS64) {
             st = launch_sweep_colour(run, p, s);
+        } else if (!g_override.lpr && string_sweep_supported(run.dim, run.L, run.layout)) {
+            st = launch_sweep_strings(run, p, s);
         } else {
             SweepConfig fc = g_override.lpr ? g_override : fast_config(run.L);
             st = launch_sweep_fast(run, p, fc.lpr, fc.wpb, s);

@@ -30,10 +30,13 @@
 // the instructions' immediate offsets.
 #include "pa_common.h"
 #include "pa_sweep_util.h"
+#include "pa_sweep_words.h"
 
 namespace pa {
 
 namespace colour {
+
+using namespace words;
 
 constexpr int L = 16;
 constexpr int NR = L * L;           // rows per replica
@@ -43,154 +46,6 @@ constexpr int PS = 8 * RPW + 4;     // dwords per plane of a wave (eight words p
                                     // staggers the four lanes of a replica over the banks)
 constexpr int ROWW = L * PS;        // dwords of a wave's rows
 constexpr int JS = 8 * 6 + 2;       // dwords of coupling masks per plane (six per word)
-
-// thresholds by class c = 4, 5, 6 (c bonds of the site with J s_i s_j = -1 in the kernel's bit
-// convention: c <= 3 flips outright)
-struct Thr {
-    uint32_t thi4, thi5, thi6;
-    uint64_t T4, T5, T6;
-};
-
-// byte B of v, times 8: the offset of entry v.byte[B] of a table of 8-byte entries (one SDWA op)
-template <int B>
-__device__ __forceinline__ uint32_t byte_x8(uint32_t v)
-{
-    uint32_t r;
-    if constexpr (B == 0)
-        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(v));
-    else if constexpr (B == 1)
-        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(v));
-    else if constexpr (B == 2)
-        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(v));
-    else
-        asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(v));
-    return r;
-}
-
-template <int B>
-__device__ __forceinline__ uint2 tab_entry(const uint2* tt, uint32_t idx_bytes)
-{
-    return *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(tt) + byte_x8<B>(idx_bytes));
-}
-
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8); }
-// bits of a where m is set, of b elsewhere: one v_bitop3_b32 (m ? a : b is truth table 0xCA), also
-// when m is not a constant (the optimiser would spend a second op on ~m)
-__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b)
-{
-    return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
-}
-
-// raw | (e << k) as one v_lshl_or_b32; k is a constant after unrolling, and the switch folds to
-// the one asm statement with k as an inline constant
-#define PA_LSHL_OR(K) \
-    case K: asm("v_lshl_or_b32 %0, %1, " #K ", %2" : "=v"(r) : "v"(e), "v"(raw)); break;
-__device__ __forceinline__ uint32_t lshl_or(uint32_t e, int k, uint32_t raw)
-{
-    uint32_t r = raw | (e << k);
-    switch (k) {
-        PA_LSHL_OR(0) PA_LSHL_OR(2) PA_LSHL_OR(4) PA_LSHL_OR(6) PA_LSHL_OR(8) PA_LSHL_OR(10) PA_LSHL_OR(12)
-        PA_LSHL_OR(14)
-        default: break;
-    }
-    return r;
-}
-#undef PA_LSHL_OR
-
-// min(saturated(b - w), 2) per 16-bit half; the min is written out, since as an expression the
-// optimiser may expand it into compares and selects per half
-__device__ __forceinline__ uint32_t first_look(uint32_t b, uint32_t w)
-{
-    typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
-    const u16x2 d = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, b), __builtin_bit_cast(u16x2, w));
-    const u16x2 two = {2, 2};
-    uint32_t e;
-    asm("v_pk_min_u16 %0, %1, %2" : "=v"(e) : "v"(d), "v"(two));
-    return e;
-}
-
-// bit-sliced count of the six bond words: c = c0 + 2 c1 + 4 c2 per bit (two full adders, a half
-// adder and a final full adder)
-__device__ __forceinline__ void bond_count(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4,
-                                           uint32_t b5, uint32_t& c0, uint32_t& c1, uint32_t& c2)
-{
-    const uint32_t s1 = xor3(b0, b1, b2), k1 = maj3(b0, b1, b2);
-    const uint32_t s2 = xor3(b3, b4, b5), k2 = maj3(b3, b4, b5);
-    c0 = s1 ^ s2;
-    const uint32_t k3 = s1 & s2;
-    c1 = xor3(k1, k2, k3);
-    c2 = maj3(k1, k2, k3);
-}
-
-// Exact decisions of first-look ties (Sec. II: the 16-bit field u is the top of a 64-bit uniform;
-// when it equals the top of the threshold, the 48 low bits decide).  A wave takes these paths when
-// any of its lanes has a tie, so they touch only the tied sites.
-//
-// General thresholds: bits = candidate sites whose field equals the top of their class, so u is
-// that top and only the low bits need drawing.  Returns the accepted ones.  Thresholds come as
-// scalars: a structure passed by value to this out-of-line call would go through private memory.
-static __device__ __noinline__ uint32_t resolve_ties(uint32_t bits, uint32_t c0, uint32_t c1, uint32_t site0,
-                                                     uint32_t rr, uint32_t ctr2, uint32_t k0, uint32_t k1,
-                                                     uint32_t thi4, uint32_t thi5, uint32_t thi6, uint64_t T4,
-                                                     uint64_t T5, uint64_t T6)
-{
-    uint32_t racc = 0;
-    while (bits) {
-        const int b = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
-        const uint32_t u = cls == 0 ? thi4 : (cls == 1 ? thi5 : thi6);
-        const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
-        // site (i, k) of the word: bit 8 i + k, index site0 + 32 i + 2 k
-        const uint32_t site = site0 + 32u * (uint32_t)(b >> 3) + 2u * (uint32_t)(b & 7);
-        racc |= (uint32_t)tie_accept(u, T, site, rr, ctr2, k0, k1) << b;
-    }
-    return racc;
-}
-
-// Every top zero: a candidate accepts only if u = 0 and its low bits fall below the threshold.
-// rows: the rows (bit i) whose fields hold a zero; their Philox calls are drawn again.
-static __device__ __noinline__ uint32_t resolve_zero_rows(uint32_t rows, uint32_t cand, uint32_t c0, uint32_t c1,
-                                                          uint32_t call0, uint32_t site0, uint32_t rr, uint32_t ctr2,
-                                                          uint32_t k0, uint32_t k1, uint64_t T4, uint64_t T5,
-                                                          uint64_t T6)
-{
-    uint32_t bits = 0;
-    while (rows) {
-        const int i = __builtin_ctz(rows);
-        rows &= rows - 1u;
-        const uint4v v = philox10(call0 + 2u * (uint32_t)i, rr, ctr2, kTagMet, k0, k1);
-        for (int k = 0; k < 8; ++k)
-            if (field16(v, k) == 0) bits |= 1u << (8 * i + k);
-    }
-    bits &= cand;
-    uint32_t racc = 0;
-    while (bits) {
-        const int b = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const int cls = (int)((c0 >> b) & 1u) + 2 * (int)((c1 >> b) & 1u);
-        const uint64_t T = cls == 0 ? T4 : (cls == 1 ? T5 : T6);
-        const uint32_t site = site0 + 32u * (uint32_t)(b >> 3) + 2u * (uint32_t)(b & 7);
-        racc |= (uint32_t)tie_accept(0u, T, site, rr, ctr2, k0, k1) << b;
-    }
-    return racc;
-}
-
-// the 16 even-x and the 16 odd-x bits of two 16-bit rows (x = row a | row b << 16) as bytes:
-// returns the even bits of row a in byte 0 and of row b in byte 2, odd bits likewise in *odd
-__device__ __forceinline__ uint32_t split_colours(uint32_t x, uint32_t* odd)
-{
-    uint32_t e = x & 0x55555555u, o = (x >> 1) & 0x55555555u;
-    e = (e | (e >> 1)) & 0x33333333u;
-    o = (o | (o >> 1)) & 0x33333333u;
-    e = (e | (e >> 2)) & 0x0F0F0F0Fu;
-    o = (o | (o >> 2)) & 0x0F0F0F0Fu;
-    e = (e | (e >> 4)) & 0x00FF00FFu;
-    o = (o | (o >> 4)) & 0x00FF00FFu;
-    *odd = o;
-    return e;
-}
 
 // The coupling masks (bit set where J = -1) of every word, by role: 0 the aligned x partner, 1 the
 // rotated one, 2 the aligned y word, 3 the funnel-shifted one, 4 and 5 the z + 1 and z - 1 words.
@@ -236,32 +91,6 @@ __device__ void build_masks(const int8_t* J, uint32_t* jt, int tid)
     w0[20] = (uint8_t)(e_z >> 16);
     w1[16] = (uint8_t)o_z;
     w1[20] = (uint8_t)(o_z >> 16);
-}
-
-// first-look bounds of four sites by their class bits: entry n (low nibble: c0 of sites 0..3, high
-// nibble: c1 of the same sites) holds (bound(site 0) | bound(site 1) << 16, bound(site 2) |
-// bound(site 3) << 16), bound = top + 1 of class c0 + 2 c1 (c = 4, 5, 6; 3 cannot occur at a
-// candidate).  The launch guarantees top <= 0xFFFE.
-__device__ void build_bounds(uint2* tt, const Thr& th, int tid, int nthr)
-{
-    const uint32_t b[4] = {th.thi4 + 1u, th.thi5 + 1u, th.thi6 + 1u, th.thi6 + 1u};
-    for (int n = tid; n < 256; n += nthr) {
-        uint32_t a[4];
-        for (int t = 0; t < 4; ++t) a[t] = ((n >> t) & 1) | (((n >> (4 + t)) & 1) << 1);
-        tt[n] = make_uint2(b[a[0]] | (b[a[1]] << 16), b[a[2]] | (b[a[3]] << 16));
-    }
-}
-
-// inverse: bytes 0 and 2 of e (even x) and of o (odd x) back to two 16-bit rows
-__device__ __forceinline__ uint32_t merge_colours(uint32_t e, uint32_t o)
-{
-    e = (e | (e << 4)) & 0x0F0F0F0Fu;
-    o = (o | (o << 4)) & 0x0F0F0F0Fu;
-    e = (e | (e << 2)) & 0x33333333u;
-    o = (o | (o << 2)) & 0x33333333u;
-    e = (e | (e << 1)) & 0x55555555u;
-    o = (o | (o << 1)) & 0x55555555u;
-    return e | (o << 1);
 }
 
 // The group's rows between HBM (bit-packed: row rho of replica r of group g is the 16-bit word
@@ -329,10 +158,6 @@ __device__ void group_io(const pa_state* st, int64_t g, uint32_t* rows, int64_t 
     }
 }
 
-struct Lane {
-    uint32_t rr, ctr2, k0, k1;
-};
-
 // one colour phase of the two words W(sigma, RHO, h), h = 0, 1, of plane z (rows: the lane's
 // replica column of its wave's rows)
 template <int MODE, int RHO>
@@ -365,74 +190,10 @@ __device__ __forceinline__ void update_words(uint32_t* rows, const uint32_t* jt,
         bond_count(xor3(w, p, J[0]), xor3(w, pr, J[1]), xor3(w, ya, J[2]), xor3(w, ys, J[3]), xor3(w, zpw[h * RPW], J[4]),
                    xor3(w, zmw[h * RPW], J[5]), c0, c1, c2);
         const uint32_t call0 = (uint32_t)(L * z + RHO + 8 * h);  // row i: call0 + 2 i
-        uint32_t nw;
-        if constexpr (MODE == 2) {
-            // every top of c >= 4 is zero: candidates reject unless u = 0 (a tie).  The minimum field
-            // of each row, then of the word
-            typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
-            u16x2 m[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint4v v = philox10(call0 + 2 * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-                m[i] = __builtin_elementwise_min(
-                    __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.x), __builtin_bit_cast(u16x2, v.y)),
-                    __builtin_elementwise_min(__builtin_bit_cast(u16x2, v.z), __builtin_bit_cast(u16x2, v.w)));
-            }
-            const u16x2 zmin = __builtin_elementwise_min(__builtin_elementwise_min(m[0], m[1]),
-                                                         __builtin_elementwise_min(m[2], m[3]));
-            nw = w ^ ~c2;
-            if (zmin.x == 0 || zmin.y == 0) {
-                uint32_t rows = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) rows |= (uint32_t)(m[i].x == 0 || m[i].y == 0) << i;
-                const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
-                nw = w ^ (~c2 | resolve_zero_rows(rows, c2, c0, c1, call0, site0, c.rr, c.ctr2, c.k0, c.k1, th.T4,
-                                                  th.T5, th.T6));
-            }
-        } else {
-            // class bits of sites k = 0..3 (lo) and 4..7 (hi) of row i as byte i: c0 in the low nibble,
-            // c1 in the high one
-            const uint32_t cl = select_bits(0x0F0F0F0Fu, c0, c1 << 4);
-            const uint32_t ch = select_bits(0x0F0F0F0Fu, c0 >> 4, c1);
-            // outcomes: row i's Philox word j (sites 2 j, 2 j + 1) at 2 j + 8 (i & 1) and 16 higher, rows
-            // 0, 1 in ra and rows 2, 3 in rb
-            uint32_t ra = 0, rb = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint4v v = philox10(call0 + 2 * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
-                uint2 bl, bh;
-                if (i == 0) { bl = tab_entry<0>(tt, cl); bh = tab_entry<0>(tt, ch); }
-                else if (i == 1) { bl = tab_entry<1>(tt, cl); bh = tab_entry<1>(tt, ch); }
-                else if (i == 2) { bl = tab_entry<2>(tt, cl); bh = tab_entry<2>(tt, ch); }
-                else { bl = tab_entry<3>(tt, cl); bh = tab_entry<3>(tt, ch); }
-                const uint32_t e0 = first_look(bl.x, v.x), e1 = first_look(bl.y, v.y);
-                const uint32_t e2 = first_look(bh.x, v.z), e3 = first_look(bh.y, v.w);
-                const int o = 8 * (i & 1);
-                uint32_t r = i < 2 ? ra : rb;
-                r = (i & 1) ? lshl_or(e0, o, r) : e0;
-                r = lshl_or(e1, o + 2, r);
-                r = lshl_or(e2, o + 4, r);
-                r = lshl_or(e3, o + 6, r);
-                if (i < 2) ra = r;
-                else rb = r;
-            }
-            // accept bits (the high bit of each field) to the sites' bits 8 i + k: rows 0, 1 even k from
-            // ra >> 1, odd k from ra >> 16; rows 2, 3 even k from rb << 15, odd k in place
-            uint32_t acc = select_bits(0x0000FFFFu, select_bits(0x5555u, ra >> 1, ra >> 16),
-                                       select_bits(0x55550000u, rb << 15, rb));
-            if (((ra | rb) & 0x55555555u) != 0) {
-                // tie bits (the low bit of each field) to the sites' bits likewise: ra's even k in place,
-                // odd k from ra >> 15; rb's even k from rb << 16, odd k from rb << 1
-                const uint32_t ties = select_bits(0x0000FFFFu, select_bits(0x5555u, ra, ra >> 15),
-                                                  select_bits(0x55550000u, rb << 16, rb << 1)) & c2;
-                if (ties) {
-                    const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
-                    acc |= resolve_ties(ties, c0, c1, site0, c.rr, c.ctr2, c.k0, c.k1, th.thi4, th.thi5, th.thi6,
-                                        th.T4, th.T5, th.T6);
-                }
-            }
-            nw = w ^ (~c2 | acc);
-        }
+        // site (i, k): x = 2 k + sigma, y = rho + 2 i + 8 h
+        const uint32_t site0 = (uint32_t)(sg + L * (RHO + 8 * h) + NR * z);
+        const uint32_t nw = decide_word<MODE, false>(w, c0, c1, c2, call0, 2u, tt, c, th,
+                                              [&]() { return WordSites{call0, 2u, site0, 2u * L, 0u}; });
         own[h * RPW] = nw;
     }
 }
@@ -513,16 +274,10 @@ int launch_sweep_colour(const pa_run& run, const SweepParams& p, hipStream_t s)
 {
     if (run.dim != 3 || run.L != colour::L || run.layout != PA_BITS64 || !fast_sweep_thresholds_ok(p))
         return PA_ERR_ARG;
-    colour::Thr th;
-    th.thi4 = p.thi[4];
-    th.thi5 = p.thi[5];
-    th.thi6 = p.thi[6];
-    th.T4 = p.T64[4];
-    th.T5 = p.T64[5];
-    th.T6 = p.T64[6];
+    const words::Thr th = words::make_thr(p);
     const int64_t blocks = (run.capacity + 63) / 64;
     if (blocks <= 0) return PA_OK;
-    if (th.thi4 == 0 && th.thi5 == 0 && th.thi6 == 0)
+    if (words::all_tops_zero(th))
         hipLaunchKernelGGL(colour::k_sweep16c<2>, dim3((unsigned)blocks), dim3(256), 0, s, run.state, p, th);
     else
         hipLaunchKernelGGL(colour::k_sweep16c<0>, dim3((unsigned)blocks), dim3(256), 0, s, run.state, p, th);

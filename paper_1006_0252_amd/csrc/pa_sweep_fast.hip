@@ -122,9 +122,6 @@ struct FastLayout {
     static constexpr size_t lds_bytes(int wpb) { return (size_t)TAB_DWORDS * 4 + (size_t)wpb * ROW_BYTES; }
 };
 
-// lanes per replica used for each lattice size (L = 2 mod 4 needs one lane per replica so
-// that the Philox phase of a plane is uniform over the wave)
-__host__ __device__ constexpr int batch_lpr(int L) { return L % 4 != 0 ? 1 : (L >= 12 ? 4 : (L >= 8 ? 2 : 1)); }
 
 // coupling masks of row rho = y + L z, entries +x, +y, +z, -x, -y, -z bonds with J = -1 (bit x)
 template <int L>
@@ -635,19 +632,13 @@ __global__ void __launch_bounds__(256) k_sweep3f(const pa_state* __restrict__ st
 // The runs' states are contiguous (state r at base + r).  Work items are (run, tile of RPW
 // replicas); k_batch_tiles lays them out in the order given by the host (position p holds run
 // order[p]) and resets the work counter; k_sweep_batch waves take items in that order.
-constexpr int kMaxBatch = 1024;
-
-struct BatchOrder {
-    uint16_t run[kMaxBatch];
-};
-
 __global__ void __launch_bounds__(256) k_batch_tiles(pa_state* base, int n_runs, BatchOrder order)
 {
     int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
     __shared__ int64_t cnt[kMaxBatch];
     for (int pos = threadIdx.x; pos < n_runs; pos += blockDim.x) {
         pa_state* st = base + order.run[pos];
-        const int rpw = 64 / batch_lpr(st->L);
+        const int rpw = batch_tile_replicas(st->L, st->layout);
         cnt[pos] = st->status ? 0 : (st->R + rpw - 1) / rpw;
         st->work_counter = 0;  // a group of equal-L runs counts its items in its first run
     }
@@ -862,6 +853,13 @@ template <int L, int LAYOUT>
 static void launch_group(pa_state* base, int pos0, int pos1, const BatchOrder& order, const SweepParams& p,
                          const FastThr& th, int mode, int64_t tiles, hipStream_t s)
 {
+    if (string_sweep_supported(3, L, LAYOUT)) {
+        // colour strings: persistent unless one item per block is forced
+        const bool persistent = g_batch_launch != 2;
+        const int64_t grid = persistent ? std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles) : tiles;
+        launch_sweep_strings_group(L, base, pos0, pos1, order, p, persistent, grid, s);
+        return;
+    }
     const size_t lds = FastLayout<L, batch_lpr(L)>::lds_bytes(1);
     const dim3 block(64);
     if (group_persistent(L)) {
@@ -919,7 +917,8 @@ int launch_sweep_batch(const pa_run* runs, int n_runs, const SweepParams& p, hip
         for (int r = 0; r < n_runs; ++r) {
             if (runs[r].L != sizes[g]) continue;
             order.run[pos++] = (uint16_t)r;
-            group_tiles[g] += (runs[r].capacity + 63) / (64 / batch_lpr(runs[r].L));
+            const int rpw = batch_tile_replicas(runs[r].L, runs[r].layout);
+            group_tiles[g] += (runs[r].capacity + rpw - 1) / rpw;
         }
         group_end[g] = pos;
     }

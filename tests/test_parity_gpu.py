@@ -125,27 +125,27 @@ def test_sweep_launch_shapes_agree(L, layout, cap):
         pa.set_sweep_config(0, 0)
 
 
-@pytest.mark.parametrize("beta", [0.05, 0.5, 1.2, 1.5, 2.5, 3.0, 6.0])
-def test_colour_kernel_matches_row_pair_kernel(beta):
-    # the default sweep of the bit-packed L = 16 cube (words of one colour) against the row-pair
-    # kernel (taken when a launch shape is forced), over 20000 replicas in 313 groups, the last one
-    # partial: the same sample bit for bit, in every first-look regime
-    R0 = 20_000
-    note(f"colour vs row-pair kernel beta={beta}")
-    out = []
-    try:
-        for cfg in ((0, 0), (4, 4)):
-            pa.set_sweep_config(*cfg)
-            run = make_run(3, 16, R0, "bits64", seed=11, dseed=2)
-            sched = pa.Schedule([0.0, beta], 4, run.n_bins, device=DEV)
-            step = sched.step(1)
-            step.t0 = 17
-            run.sweep(step)
-            out.append(run.population())
-    finally:
-        pa.set_sweep_config(0, 0)
-    (s0, E0), (s1, E1) = out
-    assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
+@pytest.mark.parametrize("L,R0", [(16, 20_000), (10, 3_001), (8, 5_000), (6, 4_111), (4, 9_000)])
+def test_colour_kernels_match_row_pair_kernel(L, R0):
+    # the default sweeps of bit-packed cubes (L = 16: words of one colour; L = 4..10: one string of
+    # each colour per replica) against the row-pair kernel (taken when a launch shape is forced),
+    # many groups, the last one partial: the same sample bit for bit, in every first-look regime
+    for beta in (0.05, 0.5, 1.2, 1.5, 2.5, 3.0, 6.0):
+        note(f"colour vs row-pair kernel L={L} R0={R0} beta={beta}")
+        out = []
+        try:
+            for cfg in ((0, 0), (4, 4) if L % 4 == 0 else (1, 2)):
+                pa.set_sweep_config(*cfg)
+                run = make_run(3, L, R0, "bits64", seed=11, dseed=2)
+                sched = pa.Schedule([0.0, beta], 4, run.n_bins, device=DEV)
+                step = sched.step(1)
+                step.t0 = 17
+                run.sweep(step)
+                out.append(run.population())
+        finally:
+            pa.set_sweep_config(0, 0)
+        (s0, E0), (s1, E1) = out
+        assert np.array_equal(s0, s1) and np.array_equal(E0, E1), f"beta={beta}"
 
 
 RESAMPLE_CASES = [(1, 64, "u8", 300), (1, 64, "bits64", 300), (3, 4, "bits64", 500), (3, 6, "u8", 400),
