@@ -9,6 +9,11 @@ traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR OUT: FETCH_SIZE and WR
     dispatch) of the sweep in the benchmark, scaled by what the same counters read for a plain
     device copy of known size (copy_calibration.py), as bytes per sweep launch.
 stats DIR: the kernel_stats table of a --kernel-trace --stats run as markdown.
+replay DIR N: the last N sweep dispatches of a --kernel-trace run and every dispatch between the
+    first and the last of them (a replayed graph): calls, total and average ms per kernel.
+batched TRACE_DIR PMC_DIR...: profile_sweep.py batched under --kernel-trace and under --pmc passes:
+    per lattice size and first-look regime the sweep launch's duration, attempts/s and the
+    lane-weighted instruction counts per attempt, as a markdown table.
 """
 from __future__ import annotations
 
@@ -126,6 +131,77 @@ def stats(d):
               f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
 
 
+# profile_sweep.py batched: attempts of one batched sweep launch (10 sweeps of every run at its
+# initial size) per lattice size; its three launches per size are regimes 0, 1, 2 in order
+def _batched_attempts():
+    sys.path.insert(0, ROOT)
+    from paper_1006_0252_amd import workloads
+
+    att = {}
+    for sp in workloads.batched_specs():
+        att[sp["L"]] = att.get(sp["L"], 0) + sp["R0"] * sp["L"] ** 3 * workloads.C3_SWEEPS
+    return att
+
+
+def _sweep_L(name):
+    import re
+
+    m = re.search(r"k_sweep\w*<(\d+),", name)
+    return int(m.group(1)) if m else None
+
+
+def batched(trace_dir, pmc_dirs):
+    att = _batched_attempts()
+    times = {}
+    for r in _rows(trace_dir, "kernel_trace.csv"):
+        L = _sweep_L(r["Kernel_Name"])
+        if L is None:
+            continue
+        times.setdefault(L, []).append((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6))
+    counts = {}
+    for d in pmc_dirs:
+        per = {}
+        for r in _rows(d, "counter_collection.csv"):
+            L = _sweep_L(r["Kernel_Name"])
+            if L is None:
+                continue
+            key = (L, int(r["Dispatch_Id"]))
+            per.setdefault(key, {})
+            per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        for L in sorted({k[0] for k in per}):
+            disp = [per[k] for k in sorted(k for k in per if k[0] == L)]
+            for reg, c in enumerate(disp):
+                counts.setdefault((L, reg), {}).update(c)
+    print("| L | regime | kernel ms | attempts/s | VALU / attempt | INT64 / attempt | SALU / attempt | LDS / attempt | VALUBusy % |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for L in sorted(times):
+        for reg, (_, ms) in enumerate(sorted(times[L])):
+            c = counts.get((L, reg), {})
+            pa = {k: v * 64 / att[L] for k, v in c.items() if k.startswith("SQ_INSTS")}
+            f = lambda k: f"{pa[k]:.2f}" if k in pa else "-"
+            busy = f"{c['VALUBusy']:.0f}" if "VALUBusy" in c else "-"
+            print(f"| {L} | {reg} | {ms:.3f} | {att[L] / (ms * 1e-3):.3g} | {f('SQ_INSTS_VALU')} | {f('SQ_INSTS_VALU_INT64')} | "
+                  f"{f('SQ_INSTS_SALU')} | {f('SQ_INSTS_LDS')} | {busy} |")
+
+
+def replay(d, n):
+    rows = sorted(_rows(d, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    sw = [r for r in rows if "k_sweep" in r["Kernel_Name"]][-n:]
+    t0, t1 = int(sw[0]["Start_Timestamp"]), int(sw[-1]["End_Timestamp"])
+    agg = {}
+    for r in rows:
+        if t0 <= int(r["Start_Timestamp"]) <= t1:
+            a = agg.setdefault(r["Kernel_Name"], [0, 0.0])
+            a[0] += 1
+            a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    tot = sum(v[1] for v in agg.values())
+    print(f"window {(t1 - t0) / 1e9:.3f} s, {len(sw)} sweep dispatches, kernel time {tot / 1e3:.3f} s")
+    print("| kernel | calls | total ms | avg ms | % of kernel time |")
+    print("|---|---|---|---|---|")
+    for name, (cnt, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:16]:
+        print(f"| `{name[:72]}` | {cnt} | {ms:.1f} | {ms / cnt:.3f} | {100 * ms / tot:.2f} |")
+
+
 def main(argv):
     if not argv:
         print(__doc__)
@@ -137,6 +213,10 @@ def main(argv):
         traffic(*rest)
     elif cmd == "stats":
         stats(rest[0])
+    elif cmd == "replay":
+        replay(rest[0], int(rest[1]))
+    elif cmd == "batched":
+        batched(rest[0], rest[1:])
     else:
         print(__doc__)
         return 2
