@@ -307,6 +307,19 @@ int pa_status(const pa_run* runs, int n_runs, int32_t* host_flags);
 /* Synchronise run->stream and copy the dynamic part of its state to the host. */
 int pa_query(const pa_run* run, pa_info* out);
 
+/* Resume runs from a checkpoint.  A run's whole state between steps is its couplings, the
+ * spins and energies of the current buffer, its records and the dynamic part of its device
+ * state (pa_info, as pa_query returns it); resampling and measurement keep nothing else across
+ * calls, and every draw is keyed by (seed, replica, sweep or step index), so a resumed run
+ * continues bit for bit as the uninterrupted one would.  Protocol: pa_init_couplings on the new
+ * buffers (same dim, L, layout, couplings kind, seeds, capacity and n_records as the
+ * checkpointed run); then the caller copies the checkpoint's couplings into J, its spins into
+ * spins[info.cur], its energies into energy[info.cur] and its records into record; then
+ * pa_resume writes infos[r] into run r's device state (stream-ordered on runs[r].stream).
+ * PA_ERR_ARG for an invalid run, cur outside {0, 1}, R or R_new outside [0, capacity], k outside
+ * [0, n_records) or initialised != 1. */
+int pa_resume(const pa_run* runs, int n_runs, const pa_info* infos);
+
 /* Message for a status code. */
 const char* pa_strerror(int code);
 

@@ -87,6 +87,22 @@ int build_thresholds(double beta, int z, uint64_t* T, uint8_t* always)
     return PA_OK;
 }
 
+// the dynamic part of a run's state, from a checkpoint (pa_resume)
+__global__ void k_resume(pa_state* st, pa_info info)
+{
+    st->R = info.R;
+    st->R_new = info.R_new;
+    st->cur = info.cur;
+    st->status = info.status;
+    st->E_lo = info.E_lo;
+    st->E_hi = info.E_hi;
+    st->k = info.k;
+    st->initialised = info.initialised;
+    st->acc = info.acc;
+    st->ln_omega = info.ln_omega;
+    st->beta = info.beta;
+}
+
 }  // namespace pa
 
 using namespace pa;
@@ -388,6 +404,21 @@ int pa_query(const pa_run* run, pa_info* out)
     out->ln_omega = h.ln_omega;
     out->beta = h.beta;
     return PA_OK;
+}
+
+int pa_resume(const pa_run* runs, int n_runs, const pa_info* infos)
+{
+    if (!runs || !infos || n_runs <= 0) return PA_ERR_ARG;
+    for (int r = 0; r < n_runs; ++r) {
+        const pa_info& in = infos[r];
+        if (check_run(runs[r]) != PA_OK) return PA_ERR_ARG;
+        if (in.cur != 0 && in.cur != 1) return PA_ERR_ARG;
+        if (in.R < 0 || in.R > runs[r].capacity || in.R_new < 0 || in.R_new > runs[r].capacity) return PA_ERR_ARG;
+        if (in.k < 0 || in.k >= runs[r].n_records || in.initialised != 1) return PA_ERR_ARG;
+    }
+    for (int r = 0; r < n_runs; ++r)
+        hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, (hipStream_t)runs[r].stream, runs[r].state, infos[r]);
+    return hip_status(hipGetLastError());
 }
 
 const char* pa_strerror(int code)

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pa_weighted_average_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P]),
     "pa_status": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, P]),
     "pa_query": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.POINTER(pa_info)]),
+    "pa_resume": (ctypes.c_int, [ctypes.POINTER(pa_run), ctypes.c_int, ctypes.POINTER(pa_info)]),
     "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pa_fill_weights": (ctypes.c_int, [ctypes.c_double, ctypes.c_int64, P]),
     "pa_thresholds": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, P, P]),
@@ -311,6 +312,40 @@ class Run:
         info = pa_info()
         check(lib().pa_query(ctypes.byref(self.desc), ctypes.byref(info)), "pa_query")
         return info
+
+    # -- checkpoint and resume (host copies of the run's whole state between steps)
+    CHECKPOINT_META = ("dim", "L", "layout", "couplings_kind", "capacity", "n_records", "R0", "seed", "disorder_seed")
+
+    def checkpoint(self):
+        """The run's state between steps as host arrays (savable with numpy.savez): the couplings,
+        the current buffer's spins and energies, the records and pa_query's dynamic state."""
+        info = self.query()  # synchronises the stream
+        out = {k: np.asarray(getattr(self, k) if hasattr(self, k) else getattr(self.desc, k)) for k in self.CHECKPOINT_META}
+        out.update({f"info_{name}": np.asarray(getattr(info, name)) for name, _ in pa_info._fields_})
+        out["J"] = self.J.cpu().numpy().copy()
+        out["spins"] = self.spins[info.cur].cpu().numpy().copy()
+        out["energy"] = self.energy[info.cur].cpu().numpy().copy()
+        out["record"] = self.record.cpu().numpy().copy()
+        return out
+
+    def resume(self, ckpt):
+        """Continue a checkpointed run in this run's buffers (same geometry, layout, couplings
+        kind, seeds, capacity and record count): pa_init_couplings, the checkpoint's arrays copied
+        in, then pa_resume."""
+        import torch
+
+        for k in self.CHECKPOINT_META:
+            mine = getattr(self, k) if hasattr(self, k) else getattr(self.desc, k)
+            if int(np.asarray(ckpt[k])) != int(mine):
+                raise ValueError(f"checkpoint {k} = {int(np.asarray(ckpt[k]))}, this run has {int(mine)}")
+        self.init()
+        info = pa_info(**{name: np.asarray(ckpt[f"info_{name}"]).item() for name, _ in pa_info._fields_})
+        with torch.cuda.stream(self.stream):
+            for dst, key in ((self.J, "J"), (self.spins[info.cur], "spins"), (self.energy[info.cur], "energy"),
+                             (self.record, "record")):
+                dst.copy_(torch.from_numpy(np.ascontiguousarray(ckpt[key], np.uint8)))
+        check(lib().pa_resume(ctypes.byref(self.desc), 1, ctypes.byref(info)), "pa_resume")
+        return self
 
     def status(self):
         flags = np.zeros(1, np.int32)
