@@ -507,6 +507,7 @@ def oracle_full_runs(args):
 
     model, nproc = cpu_info()
     out = {"cpu_model": model, "logical_cpus": nproc, "threads": o.num_threads(), "ring": oracle_ring_run(o)}
+    print(f"ring run: {out['ring']['seconds']:.3f} s; cube L=8 next (about two minutes)", file=sys.stderr, flush=True)
     J = o.couplings(3, 8, 1)
     betas = [5.0 * k / 100 for k in range(101)]
     t = time.perf_counter()
