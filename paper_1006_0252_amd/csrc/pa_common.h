@@ -138,10 +138,10 @@ int launch_sweep_fast(const pa_run& run, const SweepParams& p, int lpr, int wpb,
 // the colour-packed kernel of the bit-packed L = 16 cube (PA_ERR_ARG for any other run)
 int launch_sweep_colour(const pa_run& run, const SweepParams& p, hipStream_t s);
 // the colour-string kernel (string_sweep_supported runs): one run, or one group of equal-L runs of a
-// batch (persistent waves taking items, or one item per block)
+// batch (waves persistent waves taking items, or one item per wave for waves = the items)
 int launch_sweep_strings(const pa_run& run, const SweepParams& p, hipStream_t s);
 int launch_sweep_strings_group(int L, pa_state* base, int pos0, int pos1, const BatchOrder& order,
-                               const SweepParams& p, bool persistent, int64_t grid, hipStream_t s);
+                               const SweepParams& p, bool persistent, int64_t waves, hipStream_t s);
 // batched launchers: n runs whose device states are contiguous (runs[r].state == runs[0].state + r)
 int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s);
 int launch_hist(const pa_run* runs, int n, hipStream_t s);

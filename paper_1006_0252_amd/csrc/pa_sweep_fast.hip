@@ -854,10 +854,11 @@ static void launch_group(pa_state* base, int pos0, int pos1, const BatchOrder& o
                          const FastThr& th, int mode, int64_t tiles, hipStream_t s)
 {
     if (string_sweep_supported(3, L, LAYOUT)) {
-        // colour strings: persistent unless one item per block is forced
+        // colour strings: persistent (blocks per CU counted in waves) unless one item per wave is
+        // forced
         const bool persistent = g_batch_launch != 2;
-        const int64_t grid = persistent ? std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles) : tiles;
-        launch_sweep_strings_group(L, base, pos0, pos1, order, p, persistent, grid, s);
+        const int64_t waves = persistent ? std::min<int64_t>((int64_t)cu_count() * g_batch_blocks_per_cu, tiles) : tiles;
+        launch_sweep_strings_group(L, base, pos0, pos1, order, p, persistent, waves, s);
         return;
     }
     const size_t lds = FastLayout<L, batch_lpr(L)>::lds_bytes(1);

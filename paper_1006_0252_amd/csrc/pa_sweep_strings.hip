@@ -16,8 +16,8 @@
 // with a few ghost words on both sides holding the string's periodic continuation (refreshed after
 // each colour phase), so the z wraps need no selects and no funnel leaves the buffer.
 //
-// One lane per replica: a wave holds one 64-replica bit-packed group and walks the words of a
-// colour in step, so each word's Philox call indices are the same over the wave and the first
+// One lane per replica: a wave holds one 64-replica bit-packed group (a block holds four, sharing
+// the first-look bound table) and walks the words of a colour in step, so each word's Philox call indices are the same over the wave and the first
 // rounds of the generator run on the scalar unit.  The decision step (bond count, packed first
 // look, tie paths) is the one of the L = 16 colour-packed kernel.
 #include <algorithm>
@@ -38,7 +38,8 @@ struct Geo {
     static constexpr int NP = L * L / 2;          // bits per plane
     static constexpr int NH = L * NP;             // bits per string
     static constexpr int NW = (NH + 31) / 32;     // words per string
-    static constexpr int G = (NP + 31) / 32 + 1;  // ghost words on each side
+    static constexpr int G = NP / 32 + 1;         // ghost words on each side: a funnel by up to
+                                                  // NP bits reads words k - G .. k + G
     static constexpr int EW = NW + 2 * G;         // words of an extended string
     static constexpr int NR = L * L;              // lattice rows per replica
     static constexpr int WB = L <= 8 ? 1 : 2;     // bytes of a bit-packed row
@@ -69,13 +70,29 @@ constexpr bool ghosts_in_string()
 }
 
 // LDS of one wave: the two extended strings (word-major, replica-minor, so the 64 lanes of a word
-// load hit 64 banks), per (colour, word) the coupling masks and geometry masks, the bound table
+// load hit 64 banks) and per (colour, word) the coupling masks and geometry masks
 template <int L>
-struct Smem {
+struct WaveSmem {
     uint32_t E[2 * Geo<L>::EW * 64];
     uint32_t tab[2 * Geo<L>::NW * Geo<L>::TW];
+};
+
+// a block: WPB waves, each sweeping its own 64-replica groups, and the bound table, which depends
+// only on the step's thresholds and so serves every wave (whichever run its group belongs to)
+constexpr int WPB = 4;
+template <int L>
+struct Smem {
+    WaveSmem<L> w[WPB];
     uint2 tt[256];
 };
+
+// the block's bound table, before any wave sweeps (every thread of the block reaches the barrier)
+template <int MODE>
+__device__ __forceinline__ void block_bounds(uint2* tt, const Thr& th)
+{
+    if (MODE != 2) build_bounds(tt, th, threadIdx.x, blockDim.x);
+    __syncthreads();
+}
 
 // word q of the other string relative to word k, shifted by off bits (funnel of two words)
 template <int OFF>
@@ -235,13 +252,12 @@ __device__ __forceinline__ void replica_io(const pa_state* st, int64_t g, int la
 // N_S sweeps of the 64 replicas of bit-packed group g of one run (one wave; every lane reaches the
 // end, those past R only skip their stores)
 template <int L, int MODE>
-__device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, Smem<L>& sm, int lane,
-                                            const SweepParams& p, const Thr& th)
+__device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, WaveSmem<L>& sm, const uint2* tt,
+                                            int lane, const SweepParams& p, const Thr& th)
 {
     using Gm = Geo<L>;
     constexpr int G = Gm::G, EW = Gm::EW, NW = Gm::NW, TW = Gm::TW;
     build_tables<L>(st->J, sm.tab, lane);
-    if (MODE != 2) build_bounds(sm.tt, th, lane, 64);
     uint32_t* E0 = sm.E + lane;
     uint32_t* E1 = sm.E + EW * 64 + lane;
     replica_io<L, false>(st, g, lane, E0, E1, false);
@@ -270,7 +286,7 @@ __device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, Smem<
                            xor3(w, nb[4], T[4]), xor3(w, nb[5], T[5]), c0, c1, c2);
                 c2 &= T[11];  // bits past the string are no candidates
                 const uint32_t call0 = 4u * (uint32_t)k;
-                const uint32_t nw = decide_word<MODE, true>(w, c0, c1, c2, call0, 1u, sm.tt, c, th, [&]() {
+                const uint32_t nw = decide_word<MODE, true>(w, c0, c1, c2, call0, 1u, tt, c, th, [&]() {
                     // bit b is half-site 32 k + b: site 2 (32 k + b) + sigma
                     return WordSites{call0, 1u, 64u * (uint32_t)k, 16u, ~T[6] & T[11]};
                 });
@@ -300,20 +316,22 @@ __device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, Smem<
     wave_sync();  // the next item of a persistent wave reuses this LDS
 }
 
-// ------------------------------------------------------------------ one run: one group per block
+// ------------------------------------------------------------------ one run: one group per wave
 template <int L, int MODE>
-__global__ void __launch_bounds__(64) k_sweep_cs(const pa_state* __restrict__ st, SweepParams p, Thr th)
+__global__ void __launch_bounds__(64 * WPB) k_sweep_cs(const pa_state* __restrict__ st, SweepParams p, Thr th)
 {
     __shared__ Smem<L> sm;
     if (st->status) return;  // sticky error: the population stays as it is
-    const int64_t g = blockIdx.x;
+    block_bounds<MODE>(sm.tt, th);
+    const int wave = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * WPB + wave;
     if (g * 64 >= st->R) return;
-    sweep_group<L, MODE>(st, g, sm, threadIdx.x, p, th);
+    sweep_group<L, MODE>(st, g, sm.w[wave], sm.tt, threadIdx.x & 63, p, th);
 }
 
 // ------------------------------------------------------------------ a batch of runs
-// Items (run, 64-replica group) laid out by k_batch_tiles; the persistent form takes items from the
-// group's work counter, the grid form takes item blockIdx.x.
+// Items (run, 64-replica group) laid out by k_batch_tiles; in the persistent form every wave takes
+// items from the group's work counter, in the grid form wave w of block b takes item WPB b + w.
 __device__ __forceinline__ int find_run(const int64_t* tb, int pos0, int pos1, int64_t item)
 {
     int lo = pos0, hi = pos1;  // tb[lo] <= item < tb[hi]
@@ -326,11 +344,12 @@ __device__ __forceinline__ int find_run(const int64_t* tb, int pos0, int pos1, i
 }
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(64) k_sweep_cs_batch(pa_state* base, int pos0, int pos1, BatchOrder order,
-                                                       SweepParams p, Thr th)
+__global__ void __launch_bounds__(64 * WPB) k_sweep_cs_batch(pa_state* base, int pos0, int pos1, BatchOrder order,
+                                                             SweepParams p, Thr th)
 {
     __shared__ Smem<L> sm;
-    const int lane = threadIdx.x;
+    block_bounds<MODE>(sm.tt, th);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
     const int64_t first = tb[pos0], total = tb[pos1] - first;
     pa_state* counter = base + order.run[pos0];
@@ -344,39 +363,42 @@ __global__ void __launch_bounds__(64) k_sweep_cs_batch(pa_state* base, int pos0,
         if ((int64_t)t >= total) break;  // every wave leaves once the group's items are taken
         const int64_t item = first + (int64_t)t;
         const int lo = __builtin_amdgcn_readfirstlane(find_run(tb, pos0, pos1, item));
-        sweep_group<L, MODE>(base + order.run[lo], item - tb[lo], sm, lane, p, th);
+        sweep_group<L, MODE>(base + order.run[lo], item - tb[lo], sm.w[wave], sm.tt, lane, p, th);
     }
 }
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(64) k_sweep_cs_batch_grid(pa_state* base, int pos0, int pos1, BatchOrder order,
-                                                            SweepParams p, Thr th)
+__global__ void __launch_bounds__(64 * WPB) k_sweep_cs_batch_grid(pa_state* base, int pos0, int pos1,
+                                                                  BatchOrder order, SweepParams p, Thr th)
 {
     __shared__ Smem<L> sm;
+    block_bounds<MODE>(sm.tt, th);
+    const int wave = threadIdx.x >> 6;
     const int64_t* tb = work_ptr<int64_t>(base, work_layout(base->N, base->n_bins, base->capacity).batch);
-    const int64_t item = tb[pos0] + (int64_t)blockIdx.x;
+    const int64_t item = tb[pos0] + (int64_t)blockIdx.x * WPB + wave;
     if (item >= tb[pos1]) return;
     const int lo = __builtin_amdgcn_readfirstlane(find_run(tb, pos0, pos1, item));
-    sweep_group<L, MODE>(base + order.run[lo], item - tb[lo], sm, threadIdx.x, p, th);
+    sweep_group<L, MODE>(base + order.run[lo], item - tb[lo], sm.w[wave], sm.tt, threadIdx.x & 63, p, th);
 }
 
 template <int L>
 static int launch_solo(const pa_run& run, const SweepParams& p, const Thr& th, hipStream_t s)
 {
-    const int64_t blocks = run.capacity / 64;
+    const int64_t blocks = (run.capacity / 64 + WPB - 1) / WPB;
     if (blocks <= 0) return PA_OK;
     if (all_tops_zero(th))
-        hipLaunchKernelGGL((k_sweep_cs<L, 2>), dim3((unsigned)blocks), dim3(64), 0, s, run.state, p, th);
+        hipLaunchKernelGGL((k_sweep_cs<L, 2>), dim3((unsigned)blocks), dim3(64 * WPB), 0, s, run.state, p, th);
     else
-        hipLaunchKernelGGL((k_sweep_cs<L, 0>), dim3((unsigned)blocks), dim3(64), 0, s, run.state, p, th);
+        hipLaunchKernelGGL((k_sweep_cs<L, 0>), dim3((unsigned)blocks), dim3(64 * WPB), 0, s, run.state, p, th);
     return PA_OK;
 }
 
+// waves: the persistent form's number of waves, or the grid form's number of items
 template <int L>
 static void launch_batch(pa_state* base, int pos0, int pos1, const BatchOrder& order, const SweepParams& p,
-                         const Thr& th, bool persistent, int64_t grid, hipStream_t s)
+                         const Thr& th, bool persistent, int64_t waves, hipStream_t s)
 {
-    const dim3 g((unsigned)std::max<int64_t>(1, grid)), b(64);
+    const dim3 g((unsigned)std::max<int64_t>(1, (waves + WPB - 1) / WPB)), b(64 * WPB);
     const bool z = all_tops_zero(th);
     if (persistent) {
         if (z) hipLaunchKernelGGL((k_sweep_cs_batch<L, 2>), g, b, 0, s, base, pos0, pos1, order, p, th);
@@ -403,17 +425,17 @@ int launch_sweep_strings(const pa_run& run, const SweepParams& p, hipStream_t s)
 }
 
 // one group of equal-L runs of a batch (positions pos0 .. pos1 - 1 of the order): persistent
-// (grid waves taking items) or one item per block (grid = the group's items)
+// (waves taking items) or one item per wave (waves = the group's items)
 int launch_sweep_strings_group(int L, pa_state* base, int pos0, int pos1, const BatchOrder& order,
-                               const SweepParams& p, bool persistent, int64_t grid, hipStream_t s)
+                               const SweepParams& p, bool persistent, int64_t waves, hipStream_t s)
 {
     if (!fast_sweep_thresholds_ok(p)) return PA_ERR_ARG;
     const words::Thr th = words::make_thr(p);
     switch (L) {
-        case 4: strings::launch_batch<4>(base, pos0, pos1, order, p, th, persistent, grid, s); break;
-        case 6: strings::launch_batch<6>(base, pos0, pos1, order, p, th, persistent, grid, s); break;
-        case 8: strings::launch_batch<8>(base, pos0, pos1, order, p, th, persistent, grid, s); break;
-        case 10: strings::launch_batch<10>(base, pos0, pos1, order, p, th, persistent, grid, s); break;
+        case 4: strings::launch_batch<4>(base, pos0, pos1, order, p, th, persistent, waves, s); break;
+        case 6: strings::launch_batch<6>(base, pos0, pos1, order, p, th, persistent, waves, s); break;
+        case 8: strings::launch_batch<8>(base, pos0, pos1, order, p, th, persistent, waves, s); break;
+        case 10: strings::launch_batch<10>(base, pos0, pos1, order, p, th, persistent, waves, s); break;
         default: return PA_ERR_ARG;
     }
     return PA_OK;
