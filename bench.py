@@ -74,10 +74,57 @@ def parse():
     return p.parse_args()
 
 
+BATCH_COUNTERS = os.path.join(ROOT, "profiles", "batched_256runs_L6-10_counters.json")
+
+
+def batched_by_size(specs):
+    """Per lattice size of the batched configuration: one batched sweep launch (10 sweeps of every
+    run of that size, at its initial size) per first-look regime (beta = 0.5, 2, 4), timed live
+    with HIP events on the batch's stream; with the counted VALU instructions per attempt of the
+    committed counter summary while the colour-string kernel's sources still match it."""
+    import torch
+
+    from paper_1006_0252_amd import pa, workloads
+    from paper_1006_0252_amd.profile_summary import STRING_SOURCES, sweep_source_digest
+
+    counted = None
+    try:
+        with open(BATCH_COUNTERS) as f:
+            c = json.load(f)
+        if c.get("source_digest") == sweep_source_digest(STRING_SOURCES):
+            counted = c["by_size"]
+    except (ValueError, OSError, KeyError):
+        pass
+    out = {}
+    for L in sorted({sp["L"] for sp in specs}):
+        sub = [sp for sp in specs if sp["L"] == L]
+        batch = pa.Batch(sub, 4, layout="bits64", device="cuda:0").init()
+        sched = pa.Schedule([0.0, 0.5, 2.0, 4.0], workloads.C3_SWEEPS, batch.runs[0].n_bins, device="cuda:0")
+        att = float(sum(sp["R0"] for sp in sub)) * L ** 3 * workloads.C3_SWEEPS
+        for k in (1, 2, 3):
+            step = sched.step(k)
+            batch.sweep(step)  # warm-up launch
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(batch.stream)
+            batch.sweep(step)
+            b.record(batch.stream)
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            v = {"ms": ms, "attempts_per_s": att / (ms * 1e-3)}
+            reg = str(k - 1)
+            if counted and str(L) in counted and reg in counted[str(L)]:
+                v["valu_per_attempt"] = counted[str(L)][reg].get("SQ_INSTS_VALU")
+            out.setdefault(str(L), {})[reg] = v
+        del batch
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(args):
     """256 runs (64 realisations x 4 seeds, L in {6,8,10}, R0 in [1e4,1e5]) annealed together:
-    one persistent sweep launch per step, the whole schedule one HIP graph; value = attempts/s
-    of the graph replay (steps = the 100 temperature steps)."""
+    one sweep launch per lattice size per step, the whole schedule one HIP graph; value =
+    attempts/s of the graph replay (steps = the 100 temperature steps).  by_size_and_regime: each
+    size's sweep timed alone in each first-look regime (batched_by_size)."""
     from paper_1006_0252_amd import ensemble, workloads
 
     specs = workloads.batched_specs()
@@ -103,6 +150,8 @@ def bench_batched(args):
                     "mean_gamma": float(np.mean(w["gamma"])), "mean_binder": float(np.mean(w["binder"])),
                     "groups": groups},
     }
+    del r
+    out["by_size_and_regime"] = batched_by_size(specs)
     print(json.dumps(out), flush=True)
 
 

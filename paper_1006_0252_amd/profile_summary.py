@@ -11,9 +11,9 @@ traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR OUT: FETCH_SIZE and WR
 stats DIR: the kernel_stats table of a --kernel-trace --stats run as markdown.
 replay DIR N: the last N sweep dispatches of a --kernel-trace run and every dispatch between the
     first and the last of them (a replayed graph): calls, total and average ms per kernel.
-batched TRACE_DIR PMC_DIR...: profile_sweep.py batched under --kernel-trace and under --pmc passes:
-    per lattice size and first-look regime the sweep launch's duration, attempts/s and the
-    lane-weighted instruction counts per attempt, as a markdown table.
+batched TRACE_DIR PMC_DIR... [OUT.json]: profile_sweep.py batched under --kernel-trace and under
+    --pmc passes: per lattice size and first-look regime the sweep launch's duration, attempts/s and
+    the lane-weighted instruction counts per attempt, as a markdown table (and as JSON).
 """
 from __future__ import annotations
 
@@ -26,8 +26,12 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_colour.hip", "paper_1006_0252_amd/csrc/pa_sweep.hip",
-                 "paper_1006_0252_amd/csrc/pa_sweep_util.h", "paper_1006_0252_amd/csrc/pa_common.h", "include/pa.h")
+# the sources each sweep kernel is compiled from (a summary records their sha256; bench.py uses
+# its figures only while they are unchanged)
+SWEEP_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_colour.hip", "paper_1006_0252_amd/csrc/pa_sweep_words.h",
+                 "paper_1006_0252_amd/csrc/pa_sweep_util.h", "paper_1006_0252_amd/csrc/pa_common.h")
+STRING_SOURCES = ("paper_1006_0252_amd/csrc/pa_sweep_strings.hip", "paper_1006_0252_amd/csrc/pa_sweep_words.h",
+                  "paper_1006_0252_amd/csrc/pa_sweep_util.h", "paper_1006_0252_amd/csrc/pa_common.h")
 SWEEP_KERNEL = "k_sweep16c"
 KERNEL_LABEL = "k_sweep16c (colour-packed words, bit-packed L=16; pa_sweep, 10 sweeps per launch)"
 ATTEMPTS_PER_LAUNCH = 1_000_000 * 4096 * 10  # profile_sweep.py: R0 = 1e6 replicas, L = 16, 10 sweeps
@@ -38,9 +42,9 @@ INSTRUCTION_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_IN
                         "SQ_INSTS_VALU_INT64", "SQ_INSTS_SMEM", "SQ_INSTS_BRANCH")
 
 
-def sweep_source_digest():
+def sweep_source_digest(sources=SWEEP_SOURCES):
     h = hashlib.sha256()
-    for rel in SWEEP_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -150,7 +154,9 @@ def _sweep_L(name):
     return int(m.group(1)) if m else None
 
 
-def batched(trace_dir, pmc_dirs):
+def batched(trace_dir, pmc_dirs, out=None):
+    """out: also write the per-size, per-regime figures as JSON (with the colour-string kernel's
+    source digest), for bench.py's batched line"""
     att = _batched_attempts()
     times = {}
     for r in _rows(trace_dir, "kernel_trace.csv"):
@@ -172,6 +178,19 @@ def batched(trace_dir, pmc_dirs):
             disp = [per[k] for k in sorted(k for k in per if k[0] == L)]
             for reg, c in enumerate(disp):
                 counts.setdefault((L, reg), {}).update(c)
+    if out:
+        res = {"workload": "profile_sweep.py batched: the 256 runs at their initial sizes, one batched launch of 10 sweeps "
+                           "at beta = 0.5, 2, 4",
+               "by_size": {}, "source_digest": sweep_source_digest(STRING_SOURCES)}
+        for L in sorted(times):
+            for reg, (_, ms) in enumerate(sorted(times[L])):
+                c = counts.get((L, reg), {})
+                res["by_size"].setdefault(str(L), {})[str(reg)] = {
+                    "ms": ms, "attempts": att[L], "attempts_per_s": att[L] / (ms * 1e-3),
+                    **{k: v * 64 / att[L] for k, v in c.items() if k.startswith("SQ_INSTS")},
+                    **({"VALUBusy": c["VALUBusy"]} if "VALUBusy" in c else {})}
+        with open(out, "w") as f:
+            json.dump(res, f, indent=1)
     print("| L | regime | kernel ms | attempts/s | VALU / attempt | INT64 / attempt | SALU / attempt | LDS / attempt | VALUBusy % |")
     print("|---|---|---|---|---|---|---|---|---|")
     for L in sorted(times):
@@ -216,7 +235,8 @@ def main(argv):
     elif cmd == "replay":
         replay(rest[0], int(rest[1]))
     elif cmd == "batched":
-        batched(rest[0], rest[1:])
+        js = [a for a in rest if a.endswith(".json")]
+        batched(rest[0], [a for a in rest[1:] if not a.endswith(".json")], js[0] if js else None)
     else:
         print(__doc__)
         return 2
