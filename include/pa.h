@@ -155,6 +155,9 @@ typedef struct pa_run {
     pa_state* state;         /* one pa_state */
     void* stream;            /* hipStream_t */
 } pa_run;
+/* Every device pointer of a pa_run is 256-byte aligned (as hipMalloc returns it; the runs of a
+ * batch take consecutive pa_state blocks, sizeof(pa_state) = 256); calls return PA_ERR_ARG
+ * otherwise, before touching the device. */
 
 /* One temperature step beta_from -> beta_to (schedule index k >= 1). */
 typedef struct pa_step {

@@ -18,6 +18,9 @@ static bool geometry_ok(int dim, int L)
 static int64_t num_sites(int dim, int L) { return dim == 1 ? (int64_t)L : (int64_t)L * L * L; }
 static int64_t num_bonds(int dim, int L) { return dim == 1 ? (int64_t)L : 3 * (int64_t)L * L * L; }
 
+// the runs of a batch take consecutive pa_state blocks, each on a 256-byte boundary
+static_assert(sizeof(pa_state) == 256, "pa_state is one 256-byte block");
+
 static int check_run(const pa_run& r)
 {
     if (!geometry_ok(r.dim, r.L)) return PA_ERR_ARG;
@@ -29,6 +32,11 @@ static int check_run(const pa_run& r)
     if (!r.J || !r.spins[0] || !r.spins[1] || !r.energy[0] || !r.energy[1] || !r.counts || !r.offsets ||
         !r.work || !r.record || !r.state)
         return PA_ERR_ARG;
+    // the kernels move spins and work-buffer arrays in 16-byte pieces from 256-byte aligned bases
+    const void* bufs[] = {r.J, r.spins[0], r.spins[1], r.energy[0], r.energy[1], r.counts, r.offsets, r.work,
+                          r.record, r.state};
+    for (const void* b : bufs)
+        if ((uintptr_t)b % 256 != 0) return PA_ERR_ARG;
     // E^3 moments are summed in int64 over the population: |E| <= n_bonds
     const double B = (double)num_bonds(r.dim, r.L);
     if (B * B * B * (double)r.capacity > 9.0e18) return PA_ERR_ARG;

@@ -399,8 +399,8 @@ __global__ void __launch_bounds__(256) k_gather_u8(pa_state* base)
     }
 }
 
-// bit-packed gather: lane = destination replica, loop over rows; a row word of replica j sits
-// at (j/64 * n_rows + rho) * 64 + j mod 64 (row words of 1, 2 or 4 bytes by lattice size)
+// bit-packed gather of one replica: loop over rows; a row word of replica j sits at
+// (j/64 * n_rows + rho) * 64 + j mod 64 (row words of 1, 2 or 4 bytes by lattice size)
 // (16 loads in flight per lane: one dependent load-store pair per row leaves the copy latency-
 // bound, a few hundred bytes in flight per wave against the microseconds of HBM latency)
 template <typename Wt>
@@ -421,21 +421,6 @@ __device__ inline void gather_rows(const pa_state* st, int64_t j, int64_t rn, in
     for (; rho < n_rows; ++rho) b[(int64_t)rho * 64] = a[(int64_t)rho * 64];
 }
 
-__global__ void __launch_bounds__(256) k_gather_bits(pa_state* base)
-{
-    pa_state* st = base + blockIdx.y;
-    if (st->status) return;
-    const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (rn >= st->R_new) return;
-    const int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
-    const int64_t j = src[rn];
-    const int n_rows = st->dim == 1 ? (st->N + 31) / 32 : st->L * st->L;
-    const int WB = st->dim == 1 ? 4 : (st->L <= 8 ? 1 : (st->L <= 16 ? 2 : 4));
-    if (WB == 1) gather_rows<uint8_t>(st, j, rn, n_rows);
-    else if (WB == 2) gather_rows<uint16_t>(st, j, rn, n_rows);
-    else gather_rows<uint32_t>(st, j, rn, n_rows);
-    st->energy[st->cur ^ 1][rn] = st->energy[st->cur][j];
-}
 
 // commit an accepted step: swap the buffers, accumulate ln Q (eq. sumQ) and write record[k]; a step
 // refused by a sticky flag leaves state and records as they were
@@ -502,6 +487,76 @@ int launch_hist(const pa_run* runs, int n, hipStream_t s)
     return PA_OK;
 }
 
+// Bit-packed gather, a block of kStageThreads consecutive destination replicas at a time.  The
+// sources of consecutive destinations are non-decreasing, so the block's sources lie in a few
+// consecutive source groups; row by row (kStageRows rows per pass) the block stages those groups'
+// whole rows in LDS with 16-byte loads and each thread then takes its replica's word from LDS into
+// the destination row.  A source row is read from HBM once per block instead of once per
+// destination group that needs it (a group's sources straddle two source groups about a third of
+// the time).  A block whose sources span more than kStageGroups groups (large copy numbers next to
+// long runs of zeros) gathers per replica with gather_rows.
+constexpr int kStageThreads = 512;  // destination replicas per block (eight bit-packed groups)
+constexpr int kStageGroups = 16;
+constexpr int kStageRows = 8;
+
+template <typename Wt>
+__device__ __forceinline__ void gather_staged(pa_state* st, uint4* stage)
+{
+    constexpr int LPL = 64 * (int)sizeof(Wt) / 16;  // 16-byte pieces of a 64-replica row
+    const int64_t R_new = st->R_new;
+    const int64_t d0 = (int64_t)blockIdx.x * kStageThreads;
+    if (d0 >= R_new) return;
+    const int64_t d1 = d0 + kStageThreads - 1 < R_new ? d0 + kStageThreads - 1 : R_new - 1;
+    const int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
+    const int64_t rn = d0 + threadIdx.x;
+    const bool valid = rn < R_new;
+    const int64_t j = valid ? src[rn] : 0;
+    const int n_rows = st->dim == 1 ? (st->N + 31) / 32 : st->L * st->L;
+    const int64_t g_lo = src[d0] >> 6, g_hi = src[d1] >> 6;  // the same for every thread
+    const int cur = st->cur;
+    if (g_hi - g_lo + 1 > kStageGroups) {
+        if (valid) {
+            gather_rows<Wt>(st, j, rn, n_rows);
+            st->energy[cur ^ 1][rn] = st->energy[cur][j];
+        }
+        return;
+    }
+    const int nsrc = (int)(g_hi - g_lo + 1);
+    const uint4* A = reinterpret_cast<const uint4*>((const Wt*)st->spins[cur] + g_lo * n_rows * 64);
+    Wt* B = (Wt*)st->spins[cur ^ 1] + ((rn >> 6) * n_rows) * 64 + (rn & 63);
+    const Wt* S = reinterpret_cast<const Wt*>(stage);
+    const int64_t jl = j - g_lo * 64;  // the source's place among the staged groups' replicas
+    const int jg = (int)(jl >> 6), jo = (int)(jl & 63);
+    for (int r0 = 0; r0 < n_rows; r0 += kStageRows) {
+        const int nr = n_rows - r0 < kStageRows ? n_rows - r0 : kStageRows;
+        // staged piece e: group e / (nr LPL), row r0 + (e / LPL) mod nr, piece e mod LPL
+        for (int e = threadIdx.x; e < nsrc * nr * LPL; e += kStageThreads) {
+            const int line = e / LPL, part = e - line * LPL;
+            const int gi = line / nr, q = line - gi * nr;
+            stage[(gi * kStageRows + q) * LPL + part] = A[((int64_t)gi * n_rows + r0 + q) * LPL + part];
+        }
+        __syncthreads();
+        if (valid) {
+            for (int q = 0; q < nr; ++q) B[(int64_t)(r0 + q) * 64] = S[(jg * kStageRows + q) * 64 + jo];
+        }
+        __syncthreads();
+    }
+    if (valid) st->energy[cur ^ 1][rn] = st->energy[cur][j];
+}
+
+// one block of kStageThreads destinations of run blockIdx.y; the row word's width is the run's (a
+// batch may mix lattice sizes), the staging buffer sized for the widest
+__global__ void __launch_bounds__(kStageThreads) k_gather_bits_staged(pa_state* base)
+{
+    __shared__ uint4 stage[kStageGroups * kStageRows * 16];
+    pa_state* st = base + blockIdx.y;
+    if (st->status) return;
+    const int WB = st->dim == 1 ? 4 : (st->L <= 8 ? 1 : (st->L <= 16 ? 2 : 4));
+    if (WB == 1) gather_staged<uint8_t>(st, stage);
+    else if (WB == 2) gather_staged<uint16_t>(st, stage);
+    else gather_staged<uint32_t>(st, stage);
+}
+
 int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t s)
 {
     const BatchShape b = batch_shape(runs, n);
@@ -525,7 +580,8 @@ int launch_resample(const pa_run* runs, int n, const pa_step& step, hipStream_t 
         const int64_t threads = b.cap_max * (b.stride_max / 16);
         hipLaunchKernelGGL(k_gather_u8, dim3((unsigned)((threads + 255) / 256), n), dim3(256), 0, s, base);
     } else {
-        hipLaunchKernelGGL(k_gather_bits, dim3(cap_blocks, n), dim3(256), 0, s, base);
+        const unsigned blocks = (unsigned)((b.cap_max + kStageThreads - 1) / kStageThreads);
+        hipLaunchKernelGGL(k_gather_bits_staged, dim3(blocks, n), dim3(kStageThreads), 0, s, base);
     }
     hipLaunchKernelGGL(k_finish, dim3(1, n), dim3(1), 0, s, base, p);
     return hip_status(hipGetLastError());

@@ -88,6 +88,23 @@ def test_calls_reject_bad_runs_without_touching_the_device():
     assert pa.lib().pa_strerror(pa.PA_ERR_CAPACITY).startswith(b"resampled population")
 
 
+def test_calls_reject_unaligned_buffers_without_touching_the_device():
+    # a well-formed descriptor whose spin buffer is 8 bytes off a 256-byte boundary (the pointers
+    # are never dereferenced: the check comes first)
+    r = pa.pa_run()
+    r.dim, r.L, r.layout, r.n_records, r.capacity, r.R0, r.couplings = 3, 8, pa.PA_BITS64, 4, 128, 100, pa.PA_PM1
+    base = 1 << 40
+    r.J, r.energy[0], r.energy[1], r.counts, r.offsets = base, base + 4096, base + 8192, base + 12288, base + 16384
+    r.work, r.record, r.state = base + 20480, base + 24576, base + 28672
+    r.spins[0], r.spins[1] = base + 32768 + 8, base + 65536
+    step = pa.pa_step()
+    step.beta_from, step.beta_to, step.k, step.n_sweeps = 0.0, 0.1, 1, 1
+    L = pa.lib()
+    assert L.pa_init_couplings(ctypes.byref(r), 1, None) == pa.PA_ERR_ARG
+    assert L.pa_sweep(ctypes.byref(r), 1, ctypes.byref(step)) == pa.PA_ERR_ARG
+    assert L.pa_resample(ctypes.byref(r), 1, ctypes.byref(step)) == pa.PA_ERR_ARG
+
+
 def test_weights_equal_oracle_levels():
     # w_d = exp(-dbeta 4d): the same doubles the oracle's C libm exp gives for the level weights
     # (math.exp is the C library's exp; numpy's vectorised exp may round differently)
