@@ -86,9 +86,10 @@ __host__ __device__ inline WorkLayout work_layout(int64_t N, int64_t n_bins, int
     return w;
 }
 
-// bytes of the Gaussian sweep table after WorkLayout::total: u16 [colour][N / 2][64] (cube) or
-// [colour][N / 2][4] (chain), sized for the cube
-__host__ __device__ inline size_t gauss_table_bytes(int64_t N) { return 128 * (size_t)N; }
+// bytes of the Gaussian sweep tables after WorkLayout::total: N / 2 sites per colour times 64
+// neighbour patterns (cube; 4 for the chain, sized for the cube), a u16 first-look table and then
+// a u64 table of the full thresholds
+__host__ __device__ inline size_t gauss_table_bytes(int64_t N) { return (2 + 8) * 64 * (size_t)N; }
 
 template <typename T>
 __device__ inline T* work_ptr(const pa_state* st, size_t off)

@@ -11,6 +11,7 @@
 
 #include "pa_common.h"
 #include "pa_lattice.h"
+#include "pa_sweep_words.h"
 
 #pragma clang fp contract(off)
 
@@ -164,14 +165,21 @@ __global__ void __launch_bounds__(64) k_sweep_gauss(const pa_state* __restrict__
 // dE of an attempt depends only on the site and on the pattern b of the bits s_j xor s_i of
 // its neighbours in field order: flipping every spin negates each term of h exactly, hence h,
 // and leaves dE unchanged.  Per call, k_gauss_table tabulates for every site and pattern
-// T16 = floor(p 2^16) with p = expd(-(beta dE)) computed as in k_sweep_gauss (s_i = 0, s_j = bit
-// of b), and 0xFFFF where the flip is always accepted (dE <= 0 or p >= 1).  An attempt compares
-// its 16-bit draw u with T16: u < T16 accepts, u > T16 rejects, and u == T16 (rare) recomputes p
-// for that lane and compares the 64-bit draw with floor(p 2^64), as k_sweep_gauss does.  The
-// outcome of every attempt is therefore the same as there.
+// T64 = floor(p 2^64) with p = expd(-(beta dE)) computed as in k_sweep_gauss (s_i = 0, s_j = bit
+// of b), or all ones where the flip is always accepted (dE <= 0 or p >= 1; a p below 1 gives at
+// most 2^64 - 2^11), and its top T16 = T64 >> 48.  An attempt compares its 16-bit draw u with T16:
+// u < T16 accepts, u > T16 rejects, and u == T16 (rare) compares the 64-bit draw with T64, as
+// k_sweep_gauss does (always accepting where T64 is all ones).  The outcome of every attempt is
+// therefore the same as there.
 //
-// Table layout (after the work layout): u16 [colour c][h][pattern], h = i >> 1 for the site i of
-// colour c among i = 2h, 2h + 1 (rows have even length, so exactly one of the two has colour c).
+// Table layout (after the work layout): u16 [colour c][segment m][pattern b][k], k = 0..7 the
+// sites of colour c in segment m in ascending order.  Site i of colour c has h = i >> 1 = 8m + k
+// (rows have even length, so exactly one of 2h, 2h + 1 has colour c).  The lanes of a wave work on
+// the same segment at the same time, so lane b loads the 16-byte row [c][m][b]: one coalesced 1 KB
+// load per segment whose address does not depend on the spins, issued a step ahead.  Each
+// attempt then takes its entry from lane b = its pattern with ds_bpermute, a lane-to-lane read at
+// the latency of LDS, instead of a gather from the cache at the latency of memory.  The u64 table of
+// T64 follows in the same order.
 
 constexpr int kGaussWaves = 4;
 
@@ -210,7 +218,14 @@ __device__ __forceinline__ uint16_t* gauss_table(const pa_state* st)
     return reinterpret_cast<uint16_t*>(st->work + work_layout(st->N, st->n_bins, st->capacity).total);
 }
 
-// grid (entries / 256, runs): entry e = (c, h, b) of run blockIdx.y
+// the u64 table of full thresholds, after the NB-pattern u16 table (8-byte aligned)
+template <int NB>
+__device__ __forceinline__ uint64_t* gauss_table64(const pa_state* st)
+{
+    return reinterpret_cast<uint64_t*>(gauss_table(st) + ((size_t)st->N << NB));
+}
+
+// grid (entries / 256, runs): entry e = (c, m, b, k) of run blockIdx.y
 template <int NB>
 __global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ states, double beta)
 {
@@ -221,14 +236,16 @@ __global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ stat
     if (e >= (N << NB)) return;
     const int half = (N / 2) << NB;
     const int c = e >= half, rem = e - c * half;
-    const int hh = rem >> NB, b = rem & ((1 << NB) - 1);
+    const int b = (rem >> 3) & ((1 << NB) - 1), hh = 8 * (rem >> (NB + 3)) + (rem & 7);
     const int i0 = 2 * hh;
     const int col0 = NB == 2 ? 0 : ((i0 % L) + (i0 / L) % L + i0 / (L * L)) & 1;
     const int i = i0 + (col0 != c);
     uint64_t T64 = 0;
     const bool always = gauss_threshold(gauss_field_pattern<NB>(reinterpret_cast<const double*>(st->J), i, b, L, N),
                                         beta, &T64);
-    gauss_table(st)[e] = always ? (uint16_t)0xFFFFu : (uint16_t)(T64 >> 48);
+    if (always) T64 = ~0ull;
+    gauss_table(st)[e] = (uint16_t)(T64 >> 48);
+    gauss_table64<NB>(st)[e] = T64;
 }
 
 __device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t w)  // bytes b0..b3 in {0,1} -> b0 | b1<<1 | ...
@@ -239,6 +256,20 @@ __device__ __forceinline__ uint32_t bytes_to_bits4(uint32_t w)  // bytes b0..b3 
 __device__ __forceinline__ uint32_t bits4_to_bytes(uint32_t n)  // inverse of bytes_to_bits4
 {
     return (n * 0x00204081u) & 0x01010101u;
+}
+
+// the colour parity of segment m's first site (chain: 0; cube: (q * rows per segment + z) & 1 of
+// its segment q in z plane z)
+template <int NB, int L>
+__device__ __forceinline__ int gauss_segment_parity(int m)
+{
+    if constexpr (NB == 2) {
+        return 0;
+    } else {
+        constexpr int SP = L * L / 16, NR = 16 / L;
+        const int z = m / SP, q = m - z * SP;
+        return (q * NR + z) & 1;
+    }
 }
 
 // the neighbour words of segment m in field order, each xor the segment itself
@@ -268,7 +299,7 @@ __device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__
         X[3] = (((D << 1) & ~Mlo & 0xFFFFu) | ((D >> (L - 1)) & Mlo)) ^ D;
         X[4] = (((D << L) | (Sp >> (16 - L))) & 0xFFFFu) ^ D;
         X[5] = Szm ^ D;
-        *par = (q * NR + z) & 1;
+        *par = gauss_segment_parity<NB, L>(m);
     }
 }
 
@@ -288,72 +319,130 @@ __host__ __device__ constexpr int seg_site(int k)
     return -1;
 }
 
-// sites k and k + 4 are gathered together: their (NB + 1)-bit fields must not overlap
+// ds_bpermute takes the source lane from bits 2..7 of its byte address and ignores the others.
+// Shifted by a + 2, bit a of site j's pattern lies at bit j + a + 2, so acc >> j is a valid address
+// for site j as long as no other site of acc has a bit in j + 2 .. j + NB + 1.  (For NB = 2, bits
+// 4..7 may hold other sites' bits: lanes that agree mod 4 hold the same table row.)  The 8 sites of
+// a segment are split greedily into chains of sites at least NB apart, and one and-or chain per
+// chain builds its acc.  Evaluated at compile time.
+template <int NB, int L, int SEL>
+struct SegPlan {
+    int site[8], chain[8], n_chains;
+    uint32_t mask[8][NB];  // [chain][a]: the bits of the chain's sites taken from X[a] << (a + 2)
+    constexpr SegPlan() : site{}, chain{}, n_chains(0), mask{}
+    {
+        int last[8] = {};
+        for (int k = 0; k < 8; ++k) {
+            site[k] = seg_site<NB, L, SEL>(k);
+            int c = 0;
+            while (c < n_chains && site[k] - last[c] < NB) ++c;
+            if (c == n_chains) ++n_chains;
+            last[c] = site[k];
+            chain[k] = c;
+            for (int a = 0; a < NB; ++a) mask[c][a] |= 4u << (site[k] + a);
+        }
+    }
+};
+
+// sites 2w and 2w + 1 share one packed compare: they lie in one row, two apart, and 2w below 14
 template <int NB, int L, int SEL>
 __host__ __device__ constexpr bool seg_pairs_ok()
 {
-    for (int k = 0; k < 4; ++k)
-        if (seg_site<NB, L, SEL>(k + 4) - seg_site<NB, L, SEL>(k) < NB + 1) return false;
+    for (int w = 0; w < 4; ++w)
+        if (seg_site<NB, L, SEL>(2 * w + 1) != seg_site<NB, L, SEL>(2 * w) + 2 || seg_site<NB, L, SEL>(2 * w) > 13)
+            return false;
     return true;
 }
 
-typedef const __attribute__((address_space(1))) uint16_t* gtab_ptr;
+typedef uint32_t gu32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) gu32x4* grow_ptr;  // table rows, global memory
 
-// first half of the attempts of segment m: the table entries of its 8 sites of colour parity SEL,
-// in site order; the loads stay in flight until the entries are used
-template <int NB, int L, int SEL>
-__device__ __forceinline__ void gauss_segment_lookup(gtab_ptr Tm, const uint32_t X[NB], uint32_t thi[8])
+// v_pk_min_u16, written out: as an expression the optimiser may split it into compares per half
+__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b)
 {
-    static_assert(seg_pairs_ok<NB, L, SEL>(), "paired sites overlap");
-    // bit a of site j's pattern goes to bit j + a + 1, so the NB + 1 bits from j are the pattern
-    // times 2: the byte offset of its u16 entry
-    uint32_t P[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) P[a] = X[a] << (a + 1);
-    const __attribute__((address_space(1))) uint8_t* Tb = (const __attribute__((address_space(1))) uint8_t*)Tm;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int j = seg_site<NB, L, SEL>(k), jp = seg_site<NB, L, SEL>(k + 4);
-        uint32_t acc = 0;
-#pragma unroll
-        for (int a = 0; a < NB; ++a) acc |= P[a] & ((2u << (j + a)) | (2u << (jp + a)));
-        constexpr uint32_t mask = (2u << NB) - 2;
-        thi[k] = *(gtab_ptr)(Tb + (((j >> 1) << NB) << 1) + ((acc >> j) & mask));
-        thi[k + 4] = *(gtab_ptr)(Tb + (((jp >> 1) << NB) << 1) + ((acc >> jp) & mask));
-    }
+    uint32_t r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
-// second half: u < T16 accepts, and any u == T16 is reported in *ties (site bits); returns the flips
-template <int NB, int L, int SEL>
-__device__ __forceinline__ uint32_t gauss_segment_decide(const uint32_t thi[8], const uint4v& v, uint32_t* ties)
+// a - b per 16-bit half, saturated at zero (v_pk_sub_u16 with clamp)
+__device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b)
 {
-    uint32_t F = 0, dmin = 0xFFFFFFFFu;
-    uint32_t d[8];
+    typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
+                                                                      __builtin_bit_cast(u16x2, b)));
+}
+
+// The table entries of the 8 sites of colour parity SEL in a segment, as lane reads of the rows:
+// raw[2w] holds site 2w's entry in its low half, raw[2w + 1] site 2w + 1's in its high half (word w
+// of a row holds the entries of sites 2w and 2w + 1 for the row's pattern).  The reads stay in
+// flight until gauss_segment_decide uses them.
+template <int NB, int L, int SEL>
+__device__ __forceinline__ void gauss_segment_fetch(const uint32_t X[NB], const gu32x4& row, uint32_t raw[8])
+{
+    static_assert(seg_pairs_ok<NB, L, SEL>(), "segment sites do not pair");
+    // the lane addresses: site j's pattern in bits 2.. of acc >> j
+    constexpr SegPlan<NB, L, SEL> plan{};
+    constexpr int NC = plan.n_chains;
+    uint32_t P[NB], acc[NC];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int j = seg_site<NB, L, SEL>(k);
-        const uint32_t u = (word_of(v, j >> 2) >> (16 * ((j >> 1) & 1))) & 0xFFFFu;
-        d[k] = u - thi[k];                 // borrow (bit 31) iff u < T16; 0 iff u == T16
-        F |= (d[k] >> 31) << j;
-        dmin = min(dmin, d[k]);
+    for (int a = 0; a < NB; ++a) P[a] = X[a] << (a + 2);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        acc[c] = P[0] & plan.mask[c][0];
+#pragma unroll
+        for (int a = 1; a < NB; ++a) acc[c] |= P[a] & plan.mask[c][a];
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        raw[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(acc[plan.chain[k]] >> plan.site[k]), (int)row[k >> 1]);
+}
+
+// The attempts of the 8 sites of colour parity SEL in a segment.  Site k's draw is field k of the
+// segment's Philox call (half k & 1 of word k >> 1), the same half as its table entry, so one
+// packed compare takes sites 2w and 2w + 1.  u < T16 accepts; returns the flips (site bits), and
+// *tied is set where some site has u == T16 (those are neither flipped here nor final).
+template <int NB, int L, int SEL>
+__device__ __forceinline__ uint32_t gauss_segment_decide(const uint32_t raw[8], const uint4v& v, bool* tied)
+{
+    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+    uint32_t G = 0, tmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t thi = __builtin_amdgcn_perm(raw[2 * w + 1], raw[2 * w], 0x07060100u);  // low, high half
+        tmin = pk_min_u16(tmin, vw[w] ^ thi);  // a zero half: u == T16
+        // 1 in each half where u < T16: site 2w's bit at its site, site 2w + 1's 16 above that
+        G |= pk_min_u16(pk_sub_sat_u16(thi, vw[w]), 0x00010001u) << seg_site<NB, L, SEL>(2 * w);
+    }
+    *tied = (tmin & 0xFFFFu) == 0 || (tmin >> 16) == 0;
+    // site 2w + 1 lies two above site 2w (and every site 2w below 14): the high bits move down 14
+    return (G & 0xFFFFu) | (G >> 14);
+}
+
+// the sites of colour parity SEL in a segment with u == T16
+template <int NB, int L, int SEL>
+__device__ __forceinline__ uint32_t gauss_segment_ties(const uint32_t raw[8], const uint4v& v)
+{
+    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
     uint32_t tie = 0;
-    if (dmin == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) tie |= (uint32_t)(d[k] == 0) << seg_site<NB, L, SEL>(k);
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t x = vw[w] ^ __builtin_amdgcn_perm(raw[2 * w + 1], raw[2 * w], 0x07060100u);
+        tie |= (uint32_t)((x & 0xFFFFu) == 0) << seg_site<NB, L, SEL>(2 * w);
+        tie |= (uint32_t)((x >> 16) == 0) << seg_site<NB, L, SEL>(2 * w + 1);
     }
-    *ties = tie;
-    return F;
+    return tie;
 }
 
 struct GaussWords { uint32_t w[6]; };
 
-// exact decision of the attempts in ties (u == T16): recompute p and compare 64-bit draws
+// The exact decisions of one lane's tied sites of segment m (site bits ties; X the segment's
+// neighbour words, T64m its rows of the u64 table): the 64-bit draw U = (u << 48) | 48 bits of the
+// tie stream against T64 (Sec. II).
 template <int NB>
-__device__ __attribute__((noinline)) uint32_t gauss_resolve_ties(const double* __restrict__ J, int L, int N, int m,
-                                                                  GaussWords X, uint4v v, uint32_t ties,
-                                                                  double beta, uint32_t rr, uint32_t ctr2,
-                                                                  uint32_t k0, uint32_t k1)
+__device__ __forceinline__ uint32_t gauss_resolve_ties(const uint64_t* __restrict__ T64m, GaussWords X, uint4v v,
+                                                       uint32_t ties, int m, uint32_t rr, uint32_t ctr2, uint32_t k0,
+                                                       uint32_t k1)
 {
     uint32_t F = 0;
     while (ties) {
@@ -361,27 +450,74 @@ __device__ __attribute__((noinline)) uint32_t gauss_resolve_ties(const double* _
         ties &= ties - 1;
         int b = 0;
         for (int a = 0; a < NB; ++a) b |= (int)((X.w[a] >> j) & 1u) << a;
-        const int i = 16 * m + j;
-        uint64_t T64 = 0;
-        bool accept = gauss_threshold(gauss_field_pattern<NB>(J, i, b, L, N), beta, &T64);
-        if (!accept) {
-            const uint32_t u = (word_of(v, j >> 2) >> (16 * ((j >> 1) & 1))) & 0xFFFFu;
-            const uint4v w = philox10((uint32_t)i, rr, ctr2, kTagTie, k0, k1);
-            const uint64_t U = ((uint64_t)u << 48) | (uint64_t)w.x | ((uint64_t)(w.y & 0xFFFFu) << 32);
-            accept = U < T64;
-        }
-        F |= (uint32_t)accept << j;
+        const int k = j >> 1;  // site j is the k-th of its colour in the segment
+        const uint64_t T = T64m[(b << 3) + k];
+        const uint32_t u = (word_of(v, k >> 1) >> (16 * (k & 1))) & 0xFFFFu;
+        const uint4v w = philox10((uint32_t)(16 * m + j), rr, ctr2, kTagTie, k0, k1);
+        const uint64_t U = ((uint64_t)u << 48) | (uint64_t)w.x | ((uint64_t)(w.y & 0xFFFFu) << 32);
+        F |= (uint32_t)(T == ~0ull || U < T) << j;
     }
     return F;
+}
+
+// segments per group of the tabled sweep: consecutive segments of one colour parity (cube side 8:
+// the four segments of a z plane share it; side 4 alternates; chains: one, as N / 16 may be odd)
+template <int NB, int L>
+__host__ __device__ constexpr int gauss_group()
+{
+    return NB == 6 && L == 8 ? 2 : 1;
+}
+
+// The attempts of segments m0 .. m0 + G - 1, all of colour parity SEL (rows: their table rows).
+// The rare first-look ties are decided exactly before a segment is written, from its neighbour
+// words formed again (its own word has not changed).
+template <int NB, int L, int SEL, int G>
+__device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int m0, int nseg, const gu32x4 (&rows)[G],
+                                                 const uint64_t* __restrict__ T64c, uint32_t rr, uint32_t ctr2,
+                                                 uint32_t k0, uint32_t k1)
+{
+    uint32_t D[G], raw[G][8];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        D[g] = seg[(m0 + g) * 64];
+        uint32_t X[NB];
+        int par;
+        gauss_segment_words<NB, L>(seg, m0 + g, nseg, D[g], X, &par);
+        gauss_segment_fetch<NB, L, SEL>(X, rows[g], raw[g]);
+    }
+    uint4v v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = words::philox10_lane((uint32_t)(m0 + g), rr, ctr2, kTagMet, k0, k1);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int m = m0 + g;
+        bool tied;
+        uint32_t F = gauss_segment_decide<NB, L, SEL>(raw[g], v[g], &tied);
+        if (__ballot(tied)) {
+            const uint32_t ties = gauss_segment_ties<NB, L, SEL>(raw[g], v[g]);
+            if (ties) {
+                uint32_t X[NB];
+                int par;
+                gauss_segment_words<NB, L>(seg, m, nseg, D[g], X, &par);
+                GaussWords xw = {};
+#pragma unroll
+                for (int a = 0; a < NB; ++a) xw.w[a] = X[a];
+                F |= gauss_resolve_ties<NB>(T64c + ((size_t)m << (NB + 3)), xw, v[g], ties, m, rr, ctr2, k0, k1);
+            }
+        }
+        seg[m * 64] = (uint16_t)(D[g] ^ F);
+    }
 }
 
 // 1-D grid of blocks of kGaussWaves independent waves; block -> (run, group of kGaussWaves tiles):
 // with 8 or more runs, the runs are split into 8 contiguous ranges and the blocks of range x are
 // those with id = x mod 8 (blocks go round-robin to the 8 XCDs, so a run's table stays in one
-// L2); LDS per wave: segments [N / 16][64]
+// L2); LDS per wave: segments [N / 16][64].  Every lane of a wave takes part in the lane reads of
+// the table (lanes past R compute on zero spins and store nothing), so no branch may split a wave
+// around them.
 template <int NB, int L>
 __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* __restrict__ states, int n_runs,
-                                                                      int groups, double beta, int64_t t0, int ns)
+                                                                      int groups, int64_t t0, int ns)
 {
     int run, group;
     if (n_runs >= 8) {
@@ -401,10 +537,11 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
     const int64_t R = st->R;
     if (tile * 64 >= R) return;
     extern __shared__ uint16_t lds16[];
-    const int N = st->N, Ld = st->L;
+    const int N = st->N;
     const int nseg = N >> 4;
     const double* __restrict__ J = reinterpret_cast<const double*>(st->J);
     const uint16_t* __restrict__ Tab = gauss_table(st);
+    const uint64_t* __restrict__ Tab64 = gauss_table64<NB>(st);
     uint16_t* seg = lds16 + wave * nseg * 64 + lane;
     const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
     const int64_t r = tile * 64 + lane;
@@ -420,35 +557,32 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
         seg[m * 64] = (uint16_t)w;
     }
     const uint32_t rr = (uint32_t)r;
+    const int prow = lane & ((1 << NB) - 1);  // the pattern whose table entries this lane holds
     for (int64_t t = t0; t < t0 + ns; ++t) {
         for (int col = 0; col < 2; ++col) {
             const uint32_t ctr2 = (uint32_t)(2 * t + col);
-            const uint16_t* T = Tab + (col ? ((N / 2) << NB) : 0);
-            uint4v v = philox10(0u, rr, ctr2, kTagMet, k0, k1);
-#pragma unroll 1
-            for (int m = 0; m < nseg; ++m) {
-                const uint32_t D = seg[m * 64];
-                uint32_t X[NB];
-                int par;
-                gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
-                const gtab_ptr Tm = (gtab_ptr)(T + ((8 * m) << NB));
-                uint32_t thi[8];
-                const bool sel0 = (par ^ col) == 0;
-                if (sel0) gauss_segment_lookup<NB, L, 0>(Tm, X, thi);
-                else gauss_segment_lookup<NB, L, 1>(Tm, X, thi);
-                // the next segment's draws while the table loads are in flight
-                const uint4v vn = philox10((uint32_t)(m + 1 < nseg ? m + 1 : m), rr, ctr2, kTagMet, k0, k1);
-                uint32_t ties, F;
-                if (sel0) F = gauss_segment_decide<NB, L, 0>(thi, v, &ties);
-                else F = gauss_segment_decide<NB, L, 1>(thi, v, &ties);
-                if (ties) {
-                    GaussWords xw = {};
+            // this lane's row of segment m is T[m << NB]
+            const grow_ptr T = (grow_ptr)(Tab + (col ? ((N / 2) << NB) : 0)) + prow;
+            // groups of G segments of one colour parity: their table rows (loaded a group ahead),
+            // the lane reads of their entries, their draws while those are in flight, then the
+            // decisions
+            constexpr int G = gauss_group<NB, L>();
+            const uint64_t* __restrict__ T64c = Tab64 + (col ? ((N / 2) << NB) : 0);
+            gu32x4 rows[G];
 #pragma unroll
-                    for (int a = 0; a < NB; ++a) xw.w[a] = X[a];
-                    F |= gauss_resolve_ties<NB>(J, Ld, N, m, xw, v, ties, beta, rr, ctr2, k0, k1);
-                }
-                seg[m * 64] = (uint16_t)(D ^ F);
-                v = vn;
+            for (int g = 0; g < G; ++g) rows[g] = T[g << NB];
+#pragma unroll 1
+            for (int m0 = 0; m0 < nseg; m0 += G) {
+                const int n0 = m0 + G < nseg ? m0 + G : m0;
+                gu32x4 next[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) next[g] = T[(n0 + g) << NB];
+                if ((gauss_segment_parity<NB, L>(m0) ^ col) == 0)
+                    gauss_group_step<NB, L, 0, G>(seg, m0, nseg, rows, T64c, rr, ctr2, k0, k1);
+                else
+                    gauss_group_step<NB, L, 1, G>(seg, m0, nseg, rows, T64c, rr, ctr2, k0, k1);
+#pragma unroll
+                for (int g = 0; g < G; ++g) rows[g] = next[g];
             }
         }
     }
@@ -461,8 +595,7 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
         int par;
         gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
         const double* Jm = J + (NB == 2 ? 16 * m : 48 * m);
-        // unrolled further, the couplings of the whole segment are held in VGPRs and the kernel
-        // drops from 5 to 4 waves per SIMD
+        // unrolled by 4 only: unrolled fully, the couplings of a whole segment would be held in VGPRs
 #pragma unroll 4
         for (int j = 0; j < 16; ++j) {
             if constexpr (NB == 2) {
@@ -571,11 +704,11 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
         if (blocks > INT32_MAX) return PA_ERR_ARG;
         const dim3 grid((unsigned)blocks), block(kGaussWaves * 64);
         if (dim == 1)
-            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         else if (L == 4)
-            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 4>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 4>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         else
-            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 8>), grid, block, lds, str, base, n, groups, step.beta_to, step.t0, step.n_sweeps);
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 8>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         return hip_status(hipGetLastError());
     };
     if (consecutive) {

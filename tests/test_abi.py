@@ -67,10 +67,11 @@ def test_buffer_sizes_gaussian():
     assert s.J_bytes == 8 * 3 * 512 and s.energy_bytes == 8 * 128
     p = pa.buffer_sizes(3, 8, pa.PA_U8, 128, 5)
     assert p.J_bytes == 3 * 512 and p.energy_bytes == 4 * 128 and p.spins_bytes == s.spins_bytes
-    # the Gaussian work buffer also holds the sweep's u16 table [2 colours][N / 2][64 patterns]
-    assert s.work_bytes - p.work_bytes == 2 * 2 * 256 * 64
+    # the Gaussian work buffer also holds the sweep's tables over [2 colours][N / 2][64 patterns]:
+    # u16 first-look entries and u64 thresholds
+    assert s.work_bytes - p.work_bytes == (2 + 8) * 2 * 256 * 64
     c = pa.buffer_sizes(1, 256, pa.PA_U8, 128, 5, couplings=pa.PA_GAUSS)
-    assert c.work_bytes - pa.buffer_sizes(1, 256, pa.PA_U8, 128, 5).work_bytes >= 2 * 2 * 128 * 4
+    assert c.work_bytes - pa.buffer_sizes(1, 256, pa.PA_U8, 128, 5).work_bytes >= (2 + 8) * 2 * 128 * 4
 
 
 def test_calls_reject_bad_runs_without_touching_the_device():

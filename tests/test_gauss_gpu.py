@@ -164,6 +164,42 @@ def test_batch_matches_oracle(graph):
             assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
 
 
+def test_ensemble_sizes_match_oracle():
+    # the 3D ensemble's sizes (R = 2000, 100 sweeps per step, eight runs in one launch so that runs
+    # are spread over the XCDs) for a start at T = 2 and five steps: about 10^9 attempts per run, so
+    # that the rare first-look ties (one attempt in 2^16) are decided exactly many times over
+    from paper_1006_0252_amd import gauss3d
+
+    M, R0, ns, K = 8, 2000, 100, 5
+    betas = gauss3d.schedule(100)
+    note(f"gauss ensemble sizes: {M} runs, R0={R0}, {ns} sweeps, {K} steps")
+    specs = [dict(dim=3, L=8, R0=R0, seed=1 + i, disorder_seed=1, couplings="gauss") for i in range(M)]
+    batch = pa.Batch(specs, len(betas), layout="u8", device=DEV, capacity_factor=1.25)
+    batch.init()
+    sched = pa.Schedule(betas, ns, batch.runs[0].n_bins, device=DEV)
+    batch.sweep(sched.start_sweeps())
+    for k in range(1, K + 1):
+        st = sched.step(k)
+        batch.resample(st)
+        batch.sweep(st)
+    code, flags = batch.status()
+    assert code == pa.PA_OK and not flags.any()
+    J = o.couplings_gauss(3, 8, 1)
+    for r in (0, 5):
+        s_o, E_o = o.init_replicas_gauss(3, 8, J, 1 + r, 0, R0)
+        o.sweep_replicas_gauss(3, 8, J, 1 + r, betas[0], 0, s_o, E_o, (len(betas) - 1) * ns, ns)
+        rec = batch.runs[r].records()
+        for k in range(1, K + 1):
+            st_o, c, S, lnQ, _ = o.copy_numbers_gauss(1 + r, k, betas[k - 1], betas[k], float(R0), E_o)
+            assert st_o == 0
+            keep = np.repeat(np.arange(len(E_o)), c)
+            s_o, E_o = np.ascontiguousarray(s_o[keep]), np.ascontiguousarray(E_o[keep])
+            o.sweep_replicas_gauss(3, 8, J, 1 + r, betas[k], 0, s_o, E_o, (k - 1) * ns, ns)
+            assert abs(rec[k][1] - lnQ) <= 1e-12 * max(1.0, abs(lnQ)), (r, k)
+        s, E = batch.runs[r].population()
+        assert np.array_equal(s, s_o) and np.array_equal(E, E_o), r
+
+
 def test_overlap_of_gaussian_pair():
     note("gauss overlap pair")
     RA, RB = 150, 170
