@@ -30,15 +30,20 @@ __global__ void __launch_bounds__(64) k_moments(pa_state* base)
     for (int i = ilo + threadIdx.x; i <= ihi; i += 64) s1 += hist[i] * (int64_t)(Eb + 4 * i);
     for (int off = 32; off > 0; off >>= 1) s1 += __shfl_xor(s1, off, 64);
     const double mean = (double)s1 / (double)R;
-    if (threadIdx.x != 0) return;
+    // central moments: strided partial sums over the bins, then a butterfly over the wave
     double m2 = 0.0, m3 = 0.0;
-    for (int i = ilo; i <= ihi; ++i) {
+    for (int i = ilo + threadIdx.x; i <= ihi; i += 64) {
         const int64_t h = hist[i];
         if (!h) continue;
         const double d = (double)(Eb + 4 * i) - mean;
         m2 += (double)h * (d * d);
         m3 += (double)h * (d * d * d);
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        m2 += __shfl_xor(m2, off, 64);
+        m3 += __shfl_xor(m3, off, 64);
+    }
+    if (threadIdx.x != 0) return;
     m2 /= (double)R;
     m3 /= (double)R;
     pa_record* rec = st->record + st->k;
