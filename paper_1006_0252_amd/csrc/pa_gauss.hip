@@ -258,6 +258,19 @@ __device__ __forceinline__ uint32_t bits4_to_bytes(uint32_t n)  // inverse of by
     return (n * 0x00204081u) & 0x01010101u;
 }
 
+// A lane's segments in LDS: segments 2p and 2p + 1 are the low and high halves of the lane's
+// 32-bit word of pair p, and the words of a wave's 64 lanes lie side by side ([pair][lane]), so a
+// pair is one ds_read_b32 without bank conflicts.  seg points at the lane's word of pair 0.
+__device__ __forceinline__ uint16_t& seg_at(uint16_t* seg, int m)
+{
+    return seg[(m >> 1) * 128 + (m & 1)];
+}
+
+__device__ __forceinline__ uint32_t pair_at(const uint16_t* seg, int p)
+{
+    return *reinterpret_cast<const uint32_t*>(seg + p * 128);
+}
+
 // the colour parity of segment m's first site (chain: 0; cube: (q * rows per segment + z) & 1 of
 // its segment q in z plane z)
 template <int NB, int L>
@@ -274,12 +287,12 @@ __device__ __forceinline__ int gauss_segment_parity(int m)
 
 // the neighbour words of segment m in field order, each xor the segment itself
 template <int NB, int L>
-__device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__ seg, int m, int nseg, uint32_t D,
+__device__ __forceinline__ void gauss_segment_words(uint16_t* __restrict__ seg, int m, int nseg, uint32_t D,
                                                     uint32_t X[NB], int* par)
 {
     if constexpr (NB == 2) {
-        const uint32_t Sn = seg[(m + 1 == nseg ? 0 : m + 1) * 64];
-        const uint32_t Sp = seg[(m == 0 ? nseg - 1 : m - 1) * 64];
+        const uint32_t Sn = seg_at(seg, m + 1 == nseg ? 0 : m + 1);
+        const uint32_t Sp = seg_at(seg, m == 0 ? nseg - 1 : m - 1);
         X[0] = (((D >> 1) | (Sn << 15)) & 0xFFFFu) ^ D;
         X[1] = (((D << 1) | (Sp >> 15)) & 0xFFFFu) ^ D;
         *par = 0;
@@ -289,10 +302,10 @@ __device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__
         constexpr uint32_t Mhi = L == 4 ? 0x8888u : 0x8080u;  // x = L - 1
         constexpr uint32_t Mlo = L == 4 ? 0x1111u : 0x0101u;  // x = 0
         const int z = m / SP, q = m - z * SP;
-        const uint32_t Sn = seg[(z * SP + (q + 1 == SP ? 0 : q + 1)) * 64];
-        const uint32_t Sp = seg[(z * SP + (q == 0 ? SP - 1 : q - 1)) * 64];
-        const uint32_t Sz = seg[((z + 1 == L ? 0 : z + 1) * SP + q) * 64];
-        const uint32_t Szm = seg[((z == 0 ? L - 1 : z - 1) * SP + q) * 64];
+        const uint32_t Sn = seg_at(seg, z * SP + (q + 1 == SP ? 0 : q + 1));
+        const uint32_t Sp = seg_at(seg, z * SP + (q == 0 ? SP - 1 : q - 1));
+        const uint32_t Sz = seg_at(seg, (z + 1 == L ? 0 : z + 1) * SP + q);
+        const uint32_t Szm = seg_at(seg, (z == 0 ? L - 1 : z - 1) * SP + q);
         X[0] = (((D >> 1) & ~Mhi) | ((D << (L - 1)) & Mhi)) ^ D;
         X[1] = (((D >> L) | (Sn << (16 - L))) & 0xFFFFu) ^ D;
         X[2] = Sz ^ D;
@@ -301,6 +314,24 @@ __device__ __forceinline__ void gauss_segment_words(const uint16_t* __restrict__
         X[5] = Szm ^ D;
         *par = gauss_segment_parity<NB, L>(m);
     }
+}
+
+// Cube side 8: the neighbour words of pair p (four x rows of one z plane, segments 2p and 2p + 1 in
+// the low and high halves), each xor the pair itself, formed on whole 32-bit words.  The plane's
+// other pair So holds the rows on both y sides.
+__device__ __forceinline__ void gauss_pair_words8(const uint16_t* __restrict__ seg, int p, uint32_t D2, uint32_t So,
+                                                  uint32_t X[6])
+{
+    const int z = p >> 1, h = p & 1;  // two pairs per plane
+    const uint32_t Sz = pair_at(seg, 2 * (z == 7 ? 0 : z + 1) + h);
+    const uint32_t Szm = pair_at(seg, 2 * (z == 0 ? 7 : z - 1) + h);
+    constexpr uint32_t Mhi = 0x80808080u, Mlo = 0x01010101u;  // x = 7, x = 0 in each row byte
+    X[0] = (((D2 >> 1) & ~Mhi) | ((D2 << 7) & Mhi)) ^ D2;
+    X[1] = ((D2 >> 8) | (So << 24)) ^ D2;
+    X[2] = Sz ^ D2;
+    X[3] = (((D2 << 1) & ~Mlo) | ((D2 >> 7) & Mlo)) ^ D2;
+    X[4] = ((D2 << 8) | (So >> 24)) ^ D2;
+    X[5] = Szm ^ D2;
 }
 
 // the k-th site (k = 0..7, ascending) of colour parity SEL inside a segment (chain: j & 1; cube:
@@ -377,16 +408,18 @@ __device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b)
 // raw[2w] holds site 2w's entry in its low half, raw[2w + 1] site 2w + 1's in its high half (word w
 // of a row holds the entries of sites 2w and 2w + 1 for the row's pattern).  The reads stay in
 // flight until gauss_segment_decide uses them.
-template <int NB, int L, int SEL>
+template <int NB, int L, int SEL, int HALF = 0>
 __device__ __forceinline__ void gauss_segment_fetch(const uint32_t X[NB], const gu32x4& row, uint32_t raw[8])
 {
     static_assert(seg_pairs_ok<NB, L, SEL>(), "segment sites do not pair");
-    // the lane addresses: site j's pattern in bits 2.. of acc >> j
+    // the lane addresses: site j's pattern in bits 2.. of acc >> j (the segment in bits 16 * HALF ..
+    // of the neighbour words; shifting right by 14 - a puts bit 16 + j at j + a + 2, and the low
+    // half's bits below a + 2, which no chain takes)
     constexpr SegPlan<NB, L, SEL> plan{};
     constexpr int NC = plan.n_chains;
     uint32_t P[NB], acc[NC];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) P[a] = X[a] << (a + 2);
+    for (int a = 0; a < NB; ++a) P[a] = HALF ? X[a] >> (14 - a) : X[a] << (a + 2);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         acc[c] = P[0] & plan.mask[c][0];
@@ -461,58 +494,86 @@ __device__ __forceinline__ uint32_t gauss_resolve_ties(const uint64_t* __restric
 }
 
 // segments per group of the tabled sweep: consecutive segments of one colour parity (cube side 8:
-// the four segments of a z plane share it; side 4 alternates; chains: one, as N / 16 may be odd)
+// the four of a z plane, two pairs; side 4 alternates; chains: one, as N / 16 may be odd)
 template <int NB, int L>
 __host__ __device__ constexpr int gauss_group()
 {
-    return NB == 6 && L == 8 ? 2 : 1;
+    return NB == 6 && L == 8 ? 4 : 1;
 }
 
-// The attempts of segments m0 .. m0 + G - 1, all of colour parity SEL (rows: their table rows).
-// The rare first-look ties are decided exactly before a segment is written, from its neighbour
-// words formed again (its own word has not changed).
+// The rare first-look ties of segment m, decided exactly before it is written: the neighbour words
+// are formed again (segment m's own word has not changed) and the tied lanes compare their 64-bit
+// draws with the u64 table.
+template <int NB, int L, int SEL>
+__device__ __forceinline__ uint32_t gauss_segment_tie_flips(uint16_t* __restrict__ seg, int m, int nseg, uint32_t D,
+                                                            const uint32_t raw[8], const uint4v& v,
+                                                            const uint64_t* __restrict__ T64c, uint32_t rr,
+                                                            uint32_t ctr2, uint32_t k0, uint32_t k1)
+{
+    const uint32_t ties = gauss_segment_ties<NB, L, SEL>(raw, v);
+    if (!ties) return 0;
+    uint32_t X[NB];
+    int par;
+    gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
+    GaussWords xw = {};
+#pragma unroll
+    for (int a = 0; a < NB; ++a) xw.w[a] = X[a];
+    return gauss_resolve_ties<NB>(T64c + ((size_t)m << (NB + 3)), xw, v, ties, m, rr, ctr2, k0, k1);
+}
+
+// The attempts of segments m0 .. m0 + G - 1, all of colour parity SEL (rows: their table rows):
+// the lane reads of every segment's entries, then their draws while those are in flight, then the
+// decisions.
 template <int NB, int L, int SEL, int G>
 __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int m0, int nseg, const gu32x4 (&rows)[G],
                                                  const uint64_t* __restrict__ T64c, uint32_t rr, uint32_t ctr2,
                                                  uint32_t k0, uint32_t k1)
 {
     uint32_t D[G], raw[G][8];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        D[g] = seg[(m0 + g) * 64];
+    if constexpr (G == 4) {
+        // a z plane: its two pairs, each the other's neighbour in y; the neighbour words once per
+        // pair for both halves
+        const uint32_t A = pair_at(seg, m0 >> 1), B = pair_at(seg, (m0 >> 1) + 1);
+        uint32_t X[6];
+        gauss_pair_words8(seg, m0 >> 1, A, B, X);
+        gauss_segment_fetch<NB, L, SEL, 0>(X, rows[0], raw[0]);
+        gauss_segment_fetch<NB, L, SEL, 1>(X, rows[1], raw[1]);
+        gauss_pair_words8(seg, (m0 >> 1) + 1, B, A, X);
+        gauss_segment_fetch<NB, L, SEL, 0>(X, rows[2], raw[2]);
+        gauss_segment_fetch<NB, L, SEL, 1>(X, rows[3], raw[3]);
+        D[0] = A & 0xFFFFu;
+        D[1] = A >> 16;
+        D[2] = B & 0xFFFFu;
+        D[3] = B >> 16;
+    } else {
+        D[0] = seg_at(seg, m0);
         uint32_t X[NB];
         int par;
-        gauss_segment_words<NB, L>(seg, m0 + g, nseg, D[g], X, &par);
-        gauss_segment_fetch<NB, L, SEL>(X, rows[g], raw[g]);
+        gauss_segment_words<NB, L>(seg, m0, nseg, D[0], X, &par);
+        gauss_segment_fetch<NB, L, SEL>(X, rows[0], raw[0]);
     }
     uint4v v[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) v[g] = words::philox10_lane((uint32_t)(m0 + g), rr, ctr2, kTagMet, k0, k1);
+    uint32_t F[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int m = m0 + g;
         bool tied;
-        uint32_t F = gauss_segment_decide<NB, L, SEL>(raw[g], v[g], &tied);
-        if (__ballot(tied)) {
-            const uint32_t ties = gauss_segment_ties<NB, L, SEL>(raw[g], v[g]);
-            if (ties) {
-                uint32_t X[NB];
-                int par;
-                gauss_segment_words<NB, L>(seg, m, nseg, D[g], X, &par);
-                GaussWords xw = {};
-#pragma unroll
-                for (int a = 0; a < NB; ++a) xw.w[a] = X[a];
-                F |= gauss_resolve_ties<NB>(T64c + ((size_t)m << (NB + 3)), xw, v[g], ties, m, rr, ctr2, k0, k1);
-            }
-        }
-        seg[m * 64] = (uint16_t)(D[g] ^ F);
+        F[g] = gauss_segment_decide<NB, L, SEL>(raw[g], v[g], &tied);
+        if (__ballot(tied)) F[g] |= gauss_segment_tie_flips<NB, L, SEL>(seg, m0 + g, nseg, D[g], raw[g], v[g], T64c, rr, ctr2, k0, k1);
+    }
+    if constexpr (G == 4) {
+        *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128) = (D[0] | (D[1] << 16)) ^ (F[0] | (F[1] << 16));
+        *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128 + 128) = (D[2] | (D[3] << 16)) ^ (F[2] | (F[3] << 16));
+    } else {
+        seg_at(seg, m0) = (uint16_t)(D[0] ^ F[0]);
     }
 }
 
 // 1-D grid of blocks of kGaussWaves independent waves; block -> (run, group of kGaussWaves tiles):
 // with 8 or more runs, the runs are split into 8 contiguous ranges and the blocks of range x are
 // those with id = x mod 8 (blocks go round-robin to the 8 XCDs, so a run's table stays in one
-// L2); LDS per wave: segments [N / 16][64].  Every lane of a wave takes part in the lane reads of
+// L2); LDS per wave: pairs of segments [N / 32 rounded up][64].  Every lane of a wave takes part in the lane reads of
 // the table (lanes past R compute on zero spins and store nothing), so no branch may split a wave
 // around them.
 template <int NB, int L>
@@ -542,7 +603,8 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
     const double* __restrict__ J = reinterpret_cast<const double*>(st->J);
     const uint16_t* __restrict__ Tab = gauss_table(st);
     const uint64_t* __restrict__ Tab64 = gauss_table64<NB>(st);
-    uint16_t* seg = lds16 + wave * nseg * 64 + lane;
+    const int npair = (nseg + 1) >> 1;
+    uint16_t* seg = lds16 + wave * npair * 128 + 2 * lane;
     const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
     const int64_t r = tile * 64 + lane;
     const bool valid = r < R;
@@ -554,7 +616,7 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
             const uint4 q = *reinterpret_cast<const uint4*>(row + 16 * m);
             w = bytes_to_bits4(q.x) | (bytes_to_bits4(q.y) << 4) | (bytes_to_bits4(q.z) << 8) | (bytes_to_bits4(q.w) << 12);
         }
-        seg[m * 64] = (uint16_t)w;
+        seg_at(seg, m) = (uint16_t)w;
     }
     const uint32_t rr = (uint32_t)r;
     const int prow = lane & ((1 << NB) - 1);  // the pattern whose table entries this lane holds
@@ -590,7 +652,7 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
     double E = 0.0;
 #pragma unroll 1
     for (int m = 0; m < nseg; ++m) {
-        const uint32_t D = seg[m * 64];
+        const uint32_t D = seg_at(seg, m);
         uint32_t X[NB];
         int par;
         gauss_segment_words<NB, L>(seg, m, nseg, D, X, &par);
@@ -692,7 +754,7 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
     }
     const int dim = runs[0].dim, L = runs[0].L;
     const int N = dim == 1 ? L : L * L * L;
-    const size_t lds = (size_t)kGaussWaves * (N / 16) * 64 * 2;
+    const size_t lds = (size_t)kGaussWaves * ((N / 16 + 1) / 2) * 64 * 4;
     auto go = [&](pa_state* base, int n, int64_t capacity, hipStream_t str) {
         const dim3 tgrid((unsigned)(((N << NB) + 255) / 256), (unsigned)n);
         if (NB == 2) hipLaunchKernelGGL(k_gauss_table<2>, tgrid, dim3(256), 0, str, base, step.beta_to);
