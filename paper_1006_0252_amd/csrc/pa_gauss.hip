@@ -396,6 +396,15 @@ __device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b)
     return r;
 }
 
+// (v & m) | (w & ~m) in one v_bfi_b32 with the mask in a scalar register (as an expression, the
+// optimiser keeps the unused bits exact, which costs an and and an or per term)
+__device__ __forceinline__ uint32_t bfi_sgpr(uint32_t m, uint32_t v, uint32_t w)
+{
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(v), "v"(w));
+    return r;
+}
+
 // a - b per 16-bit half, saturated at zero (v_pk_sub_u16 with clamp)
 __device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b)
 {
@@ -420,11 +429,13 @@ __device__ __forceinline__ void gauss_segment_fetch(const uint32_t X[NB], const 
     uint32_t P[NB], acc[NC];
 #pragma unroll
     for (int a = 0; a < NB; ++a) P[a] = HALF ? X[a] >> (14 - a) : X[a] << (a + 2);
+    // only the chain's fields matter (the lane read ignores the other bits), so each neighbour word
+    // is merged in with one bit-field insert of its field bits
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        acc[c] = P[0] & plan.mask[c][0];
+        acc[c] = P[0];
 #pragma unroll
-        for (int a = 1; a < NB; ++a) acc[c] |= P[a] & plan.mask[c][a];
+        for (int a = 1; a < NB; ++a) acc[c] = bfi_sgpr(plan.mask[c][a], P[a], acc[c]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
