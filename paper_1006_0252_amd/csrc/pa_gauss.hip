@@ -334,6 +334,17 @@ __device__ __forceinline__ void gauss_pair_words8(const uint16_t* __restrict__ s
     X[5] = Szm ^ D2;
 }
 
+// Chains of an even number of segments: the neighbour words of pair p (sites 32 p .. 32 p + 31),
+// each xor the pair itself, formed on whole 32-bit words (npair pairs, periodic)
+__device__ __forceinline__ void gauss_pair_words_chain(const uint16_t* __restrict__ seg, int p, int npair, uint32_t D2,
+                                                       uint32_t X[2])
+{
+    const uint32_t Sn = pair_at(seg, p + 1 == npair ? 0 : p + 1);
+    const uint32_t Sp = pair_at(seg, p == 0 ? npair - 1 : p - 1);
+    X[0] = ((D2 >> 1) | (Sn << 31)) ^ D2;
+    X[1] = ((D2 << 1) | (Sp >> 31)) ^ D2;
+}
+
 // the k-th site (k = 0..7, ascending) of colour parity SEL inside a segment (chain: j & 1; cube:
 // (x + y) & 1 of the site inside the segment)
 template <int NB, int L, int SEL>
@@ -504,13 +515,6 @@ __device__ __forceinline__ uint32_t gauss_resolve_ties(const uint64_t* __restric
     return F;
 }
 
-// segments per group of the tabled sweep: consecutive segments of one colour parity (cube side 8:
-// the four of a z plane, two pairs; side 4 alternates; chains: one, as N / 16 may be odd)
-template <int NB, int L>
-__host__ __device__ constexpr int gauss_group()
-{
-    return NB == 6 && L == 8 ? 4 : 1;
-}
 
 // The rare first-look ties of segment m, decided exactly before it is written: the neighbour words
 // are formed again (segment m's own word has not changed) and the tied lanes compare their 64-bit
@@ -534,7 +538,9 @@ __device__ __forceinline__ uint32_t gauss_segment_tie_flips(uint16_t* __restrict
 
 // The attempts of segments m0 .. m0 + G - 1, all of colour parity SEL (rows: their table rows):
 // the lane reads of every segment's entries, then their draws while those are in flight, then the
-// decisions.
+// decisions.  G is the number of consecutive segments of one colour parity taken per step: cube
+// side 8, the four of a z plane (two pairs); chains of an even number of segments, a pair;
+// otherwise one (side 4 alternates the parity from segment to segment).
 template <int NB, int L, int SEL, int G>
 __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int m0, int nseg, const gu32x4 (&rows)[G],
                                                  const uint64_t* __restrict__ T64c, uint32_t rr, uint32_t ctr2,
@@ -556,6 +562,15 @@ __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int
         D[1] = A >> 16;
         D[2] = B & 0xFFFFu;
         D[3] = B >> 16;
+    } else if constexpr (G == 2) {
+        static_assert(NB == 2, "pairs of one parity: chains");
+        const uint32_t A = pair_at(seg, m0 >> 1);
+        uint32_t X[2];
+        gauss_pair_words_chain(seg, m0 >> 1, nseg >> 1, A, X);
+        gauss_segment_fetch<NB, L, SEL, 0>(X, rows[0], raw[0]);
+        gauss_segment_fetch<NB, L, SEL, 1>(X, rows[1], raw[1]);
+        D[0] = A & 0xFFFFu;
+        D[1] = A >> 16;
     } else {
         D[0] = seg_at(seg, m0);
         uint32_t X[NB];
@@ -573,10 +588,11 @@ __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int
         F[g] = gauss_segment_decide<NB, L, SEL>(raw[g], v[g], &tied);
         if (__ballot(tied)) F[g] |= gauss_segment_tie_flips<NB, L, SEL>(seg, m0 + g, nseg, D[g], raw[g], v[g], T64c, rr, ctr2, k0, k1);
     }
-    if constexpr (G == 4) {
+    if constexpr (G >= 2)
         *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128) = (D[0] | (D[1] << 16)) ^ (F[0] | (F[1] << 16));
+    if constexpr (G == 4)
         *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128 + 128) = (D[2] | (D[3] << 16)) ^ (F[2] | (F[3] << 16));
-    } else {
+    if constexpr (G == 1) {
         seg_at(seg, m0) = (uint16_t)(D[0] ^ F[0]);
     }
 }
@@ -587,7 +603,7 @@ __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int
 // L2); LDS per wave: pairs of segments [N / 32 rounded up][64].  Every lane of a wave takes part in the lane reads of
 // the table (lanes past R compute on zero spins and store nothing), so no branch may split a wave
 // around them.
-template <int NB, int L>
+template <int NB, int L, int G>
 __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* __restrict__ states, int n_runs,
                                                                       int groups, int64_t t0, int ns)
 {
@@ -639,7 +655,6 @@ __global__ void __launch_bounds__(kGaussWaves * 64) k_sweep_gauss_tab(pa_state* 
             // groups of G segments of one colour parity: their table rows (loaded a group ahead),
             // the lane reads of their entries, their draws while those are in flight, then the
             // decisions
-            constexpr int G = gauss_group<NB, L>();
             const uint64_t* __restrict__ T64c = Tab64 + (col ? ((N / 2) << NB) : 0);
             gu32x4 rows[G];
 #pragma unroll
@@ -776,12 +791,14 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
         const int64_t blocks = n >= 8 ? (int64_t)8 * ((n + 7) / 8) * groups : (int64_t)n * groups;
         if (blocks > INT32_MAX) return PA_ERR_ARG;
         const dim3 grid((unsigned)blocks), block(kGaussWaves * 64);
-        if (dim == 1)
-            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
+        if (dim == 1 && (N / 16) % 2 == 0)
+            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0, 2>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
+        else if (dim == 1)
+            hipLaunchKernelGGL((k_sweep_gauss_tab<2, 0, 1>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         else if (L == 4)
-            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 4>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 4, 1>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         else
-            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 8>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
+            hipLaunchKernelGGL((k_sweep_gauss_tab<6, 8, 4>), grid, block, lds, str, base, n, groups, step.t0, step.n_sweeps);
         return hip_status(hipGetLastError());
     };
     if (consecutive) {
