@@ -189,8 +189,9 @@ typedef struct pa_info {
  * too small L (1D: L >= 4; 3D: L >= 2, L <= 32), capacity not a positive multiple of 64, a
  * coupling kind other than PA_PM1 / PA_GAUSS, or Gaussian couplings with a layout other than
  * PA_U8.  Couplings take 1 byte per bond (PA_PM1) or 8 (PA_GAUSS), energies 4 or 8 bytes per
- * replica; with PA_GAUSS the work buffer also holds the sweep's threshold table (128 N bytes,
- * rewritten by every pa_sweep), so buffers must be sized with the run's coupling kind. */
+ * replica; with PA_GAUSS the work buffer also holds the sweep's threshold tables (640 N bytes:
+ * 16-bit first-look entries and 64-bit thresholds per site and neighbour pattern, rewritten by
+ * every pa_sweep), so buffers must be sized with the run's coupling kind. */
 int pa_buffer_sizes(int dim, int L, int layout, int couplings, int64_t capacity, int n_records, pa_sizes* out);
 
 /* Initialise runs (Sec. II: R0 replicas at beta = 0, each uniform over the 2^N states):
