@@ -21,6 +21,7 @@
 // rounds of the generator run on the scalar unit.  The decision step (bond count, packed first
 // look, tie paths) is the one of the L = 16 colour-packed kernel.
 #include <algorithm>
+#include <type_traits>
 
 #include "pa_common.h"
 #include "pa_sweep_util.h"
@@ -275,8 +276,7 @@ __device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, WaveS
             c.ctr2 = (uint32_t)(2 * (p.t0 + s) + col);
             uint32_t* W = col ? E1 : E0;
             const uint32_t* O = col ? E0 : E1;
-#pragma unroll 1
-            for (int k = 0; k < NW; ++k) {
+            auto word = [&](int k, auto nbytes) {
                 const uint32_t* T = sm.tab + (col * NW + k) * TW;
                 const uint32_t w = W[(G + k) * 64];
                 uint32_t nb[6];
@@ -286,12 +286,19 @@ __device__ __forceinline__ void sweep_group(const pa_state* st, int64_t g, WaveS
                            xor3(w, nb[4], T[4]), xor3(w, nb[5], T[5]), c0, c1, c2);
                 c2 &= T[11];  // bits past the string are no candidates
                 const uint32_t call0 = 4u * (uint32_t)k;
-                const uint32_t nw = decide_word<MODE, true>(w, c0, c1, c2, call0, 1u, tt, c, th, [&]() {
+                const uint32_t nw = decide_word<MODE, true, decltype(nbytes)::value>(w, c0, c1, c2, call0, 1u, tt, c, th,
+                                                                                     [&]() {
                     // bit b is half-site 32 k + b: site 2 (32 k + b) + sigma
                     return WordSites{call0, 1u, 64u * (uint32_t)k, 16u, ~T[6] & T[11]};
                 });
                 W[(G + k) * 64] = nw;
-            }
+            };
+            // a partial last word draws only the calls of its bytes with sites
+            constexpr int LASTB = (Gm::NH % 32 + 7) / 8;
+            constexpr int FULL = LASTB == 0 ? NW : NW - 1;
+#pragma unroll 1
+            for (int k = 0; k < FULL; ++k) word(k, std::integral_constant<int, 4>{});
+            if constexpr (LASTB != 0) word(NW - 1, std::integral_constant<int, LASTB>{});
             refresh_ghosts<L>(W);
         }
     }

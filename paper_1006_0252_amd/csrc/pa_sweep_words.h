@@ -253,8 +253,10 @@ static __device__ __noinline__ uint32_t resolve_zero_bytes(uint32_t bytes, uint3
 // candidate, c >= 4; clear: flips outright); returns the new word.  MODE 0: bounds from the
 // 256-entry table tt; MODE 2: every top zero.  UNIFORM_CALLS: call0 is the same over the wave
 // (philox10_lane keeps the uniform rounds on the scalar unit).  ws_fn() gives the word's WordSites
-// (only the rare tie paths need them).
-template <int MODE, bool UNIFORM_CALLS, class WS>
+// (only the rare tie paths need them).  NBYTES < 4: only bytes 0 .. NBYTES - 1 hold sites (the last
+// word of a string); the other bytes' calls are not drawn and their bits come out as non-candidates
+// would (flipped), for the caller to ignore.
+template <int MODE, bool UNIFORM_CALLS, int NBYTES = 4, class WS>
 __device__ __forceinline__ uint32_t decide_word(uint32_t w, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t call0,
                                                 uint32_t call_step, const uint2* tt, const Lane& c, const Thr& th,
                                                 WS ws_fn)
@@ -265,6 +267,11 @@ __device__ __forceinline__ uint32_t decide_word(uint32_t w, uint32_t c0, uint32_
         u16x2 m[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
+            if (i >= NBYTES) {
+                const u16x2 none = {0xFFFF, 0xFFFF};
+                m[i] = none;
+                continue;
+            }
             const uint4v v = UNIFORM_CALLS ? philox10_lane(call0 + call_step * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1)
                                            : philox10(call0 + call_step * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
             m[i] = __builtin_elementwise_min(
@@ -277,7 +284,7 @@ __device__ __forceinline__ uint32_t decide_word(uint32_t w, uint32_t c0, uint32_
         if (zmin.x == 0 || zmin.y == 0) {
             uint32_t bytes = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bytes |= (uint32_t)(m[i].x == 0 || m[i].y == 0) << i;
+            for (int i = 0; i < NBYTES; ++i) bytes |= (uint32_t)(m[i].x == 0 || m[i].y == 0) << i;
             const WordSites ws = ws_fn();
             nw = w ^ (~c2 | resolve_zero_bytes(bytes, c2, c0, c1, call0, call_step, ws.base, ws.byte_step, ws.odd,
                                                c.rr, c.ctr2, c.k0, c.k1, th.T4, th.T5, th.T6));
@@ -292,7 +299,7 @@ __device__ __forceinline__ uint32_t decide_word(uint32_t w, uint32_t c0, uint32_
         // bytes 0, 1 in ra and bytes 2, 3 in rb
         uint32_t ra = 0, rb = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NBYTES; ++i) {
             const uint4v v = UNIFORM_CALLS ? philox10_lane(call0 + call_step * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1)
                                            : philox10(call0 + call_step * i, c.rr, c.ctr2, kTagMet, c.k0, c.k1);
             uint2 bl, bh;
