@@ -62,6 +62,7 @@ __global__ void k_qhist_clear(pa_state* base)
 // Hamming distance of replica j of run A and replica j of run B, u8 layout
 __global__ void __launch_bounds__(256) k_overlap_u8(pa_state* base, const pa_state* b_given, int pair_xor)
 {
+    if (pair_xor && (blockIdx.y & 1)) return;  // a pair's distances are counted once, by its first run
     pa_state* a = base + blockIdx.y;
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
@@ -113,6 +114,7 @@ constexpr int kOverlapItems = 4;
 __global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_state* b_given, int pair_xor, int cap)
 {
     extern __shared__ uint32_t hloc[];
+    if (pair_xor && (blockIdx.y & 1)) return;  // a pair's distances are counted once, by its first run
     pa_state* a = base + blockIdx.y;
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;  // the same for the whole block
@@ -145,7 +147,8 @@ __global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_s
     }
 }
 
-// q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A
+// q^2, q^4, Gamma from the overlap histogram (d ascending), into record[k] of run A (with pair_xor,
+// both runs of a pair read the histogram of its first run)
 // one block per run: strided partial sums over the overlap histogram, then a fixed-order tree
 // reduction (P and the Gamma count are integers and exact; q2 and q4 differ from a serial sum only
 // in rounding order)
@@ -155,7 +158,8 @@ __global__ void __launch_bounds__(256) k_overlap_stats(pa_state* base, const pa_
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
     __shared__ double red[4][256];
-    const int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+    const pa_state* h = pair_xor && (blockIdx.y & 1) ? b : a;
+    const int64_t* qh = work_ptr<int64_t>(h, work_layout(h->N, h->n_bins, h->capacity).qhist);
     const int N = a->N;
     double P = 0.0, q2 = 0.0, q4 = 0.0, g = 0.0;
     for (int d = threadIdx.x; d <= N; d += blockDim.x) {
