@@ -223,11 +223,22 @@ __global__ void __launch_bounds__(256) k_normalise(pa_state* base, ResampleParam
     }
 }
 
+// the smallest n with u < C[n] (C non-decreasing, its last entries 2^32 > u).  Small means walk
+// the table from 0 (a few steps); from 2^3 on, a branch-free binary search: n counts the entries
+// <= u, eight dependent loads instead of about 2^m (a Poisson(64) block took ~64)
 __device__ inline int64_t invert_ladder(int m, uint32_t u)
 {
     const uint64_t* C = g_ladder[m - kLadderMin];
-    int64_t n = 0;
-    while (!((uint64_t)u < C[n])) ++n;
+    if (m < 3) {
+        int64_t n = 0;
+        while (!((uint64_t)u < C[n])) ++n;
+        return n;
+    }
+    static_assert(kLadderCap == 256, "binary search over 256 entries");
+    int n = 0;
+#pragma unroll
+    for (int step = 128; step > 0; step >>= 1)
+        if (C[n + step - 1] <= (uint64_t)u) n += step;
     return n;
 }
 
