@@ -179,6 +179,26 @@ def test_resample_parity(dim, L, layout, R0):
         assert close(rec[2], o.num_sites(dim, L) * math.log(2.0) + r["lnQ"])
 
 
+def test_copy_numbers_in_the_hundreds():
+    # one step of beta 0 -> 0.1 from the random start of 5000 replicas of the L = 8 cube: the lowest
+    # energies get copy numbers up to ~700, i.e. many Poisson(64) blocks and every ladder level
+    # (the binary-search inversion), every copy number against the oracle
+    dim, L, R0 = 3, 8, 5000
+    note("copy numbers in the hundreds")
+    J = o.couplings(dim, L, 3)
+    run = make_run(dim, L, R0, "bits64", n_records=4)
+    sched = pa.Schedule([0.0, 0.1], 2, run.n_bins, device=DEV)
+    so, Eo = o.init_population(dim, L, J, 7, R0, capacity=run.capacity)
+    run.resample(sched.step(1))
+    r = o.resample(dim, L, 7, 1, 0.0, 0.1, R0, R0, so, Eo, run.capacity)
+    assert r["status"] == 0 and run.query().status == 0
+    c, off = run.counts_offsets(R0)
+    assert c.max() >= 256, "the case must reach several Poisson(64) blocks"
+    assert np.array_equal(c, r["counts"]) and np.array_equal(off, r["offsets"])
+    s, E = run.population()
+    assert np.array_equal(s, r["s"][: r["R_new"]]) and np.array_equal(E, r["E"][: r["R_new"]])
+
+
 RUN_CASES = [
     ("ring C1", 1, 64, "u8", 1000, 51, 5),
     ("ring C1 bits", 1, 64, "bits64", 1000, 51, 5),
