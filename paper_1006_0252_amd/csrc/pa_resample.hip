@@ -98,6 +98,8 @@ __global__ void k_hist_clear(pa_state* base)
     }
 }
 
+constexpr int kHistLoads = 8;
+
 // histogram of the current population's energies, counted in an LDS copy of cap_bins entries
 // when the run's bins fit there (the LDS is sized for the call, whose runs may differ in size),
 // else directly in global memory
@@ -118,13 +120,22 @@ __global__ void __launch_bounds__(256) k_hist(pa_state* base, int cap_bins)
         for (int i = threadIdx.x; i < nb; i += blockDim.x) sh[i] = 0;
     __syncthreads();
     int emin = INT32_MAX, emax = INT32_MIN;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R; j += (int64_t)gridDim.x * blockDim.x) {
-        const int e = E[j];
-        const int b = (e - Eb) >> 2;
-        if (priv) atomicAdd(&sh[b], 1u);
-        else atomicAdd((unsigned long long*)&hist[b], 1ull);
-        emin = min(emin, e);
-        emax = max(emax, e);
+    // kHistLoads energies per thread are loaded before any of them is counted, so that many loads
+    // are in flight at once (a load and its count in turn wait out the memory latency each time)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j0 < R; j0 += kHistLoads * stride) {
+        int e[kHistLoads];
+#pragma unroll
+        for (int u = 0; u < kHistLoads; ++u) e[u] = j0 + u * stride < R ? E[j0 + u * stride] : 0;
+#pragma unroll
+        for (int u = 0; u < kHistLoads; ++u) {
+            if (j0 + u * stride >= R) break;
+            const int b = (e[u] - Eb) >> 2;
+            if (priv) atomicAdd(&sh[b], 1u);
+            else atomicAdd((unsigned long long*)&hist[b], 1ull);
+            emin = min(emin, e[u]);
+            emax = max(emax, e[u]);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         emin = min(emin, __shfl_xor(emin, off, 64));
@@ -491,7 +502,8 @@ int launch_hist(const pa_run* runs, int n, hipStream_t s)
     const size_t hist_lds = (size_t)cap_bins * 4;
     // few blocks: each block zeroes and scans all bins of its LDS histogram and merges the occupied
     // ones with global atomics that land on the same few bins (L = 16, 1e6 replicas: 1024 blocks
-    // 98 us, 256 blocks 29 us, 128 blocks 21 us)
+    // 98 us, 256 blocks 29 us, 128 blocks 21 us; with eight loads in flight per thread, 128 blocks
+    // 17.5 us, 256 blocks 28 us, and 64, 32, 16 blocks were slower already before)
     const unsigned hist_blocks = (unsigned)std::min<int64_t>(128, (b.cap_max + 255) / 256);
     hipLaunchKernelGGL(k_hist_clear, dim3(32, n), dim3(256), 0, s, runs[0].state);
     hipLaunchKernelGGL(k_hist, dim3(hist_blocks, n), dim3(256), hist_lds, s, runs[0].state, (int)cap_bins);
