@@ -271,6 +271,11 @@ __device__ __forceinline__ uint32_t pair_at(const uint16_t* seg, int p)
     return *reinterpret_cast<const uint32_t*>(seg + p * 128);
 }
 
+__device__ __forceinline__ void pair_store(uint16_t* seg, int p, uint32_t w)
+{
+    *reinterpret_cast<uint32_t*>(seg + p * 128) = w;
+}
+
 // the colour parity of segment m's first site (chain: 0; cube: (q * rows per segment + z) & 1 of
 // its segment q in z plane z)
 template <int NB, int L>
@@ -588,13 +593,9 @@ __device__ __forceinline__ void gauss_group_step(uint16_t* __restrict__ seg, int
         F[g] = gauss_segment_decide<NB, L, SEL>(raw[g], v[g], &tied);
         if (__ballot(tied)) F[g] |= gauss_segment_tie_flips<NB, L, SEL>(seg, m0 + g, nseg, D[g], raw[g], v[g], T64c, rr, ctr2, k0, k1);
     }
-    if constexpr (G >= 2)
-        *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128) = (D[0] | (D[1] << 16)) ^ (F[0] | (F[1] << 16));
-    if constexpr (G == 4)
-        *reinterpret_cast<uint32_t*>(seg + (m0 >> 1) * 128 + 128) = (D[2] | (D[3] << 16)) ^ (F[2] | (F[3] << 16));
-    if constexpr (G == 1) {
-        seg_at(seg, m0) = (uint16_t)(D[0] ^ F[0]);
-    }
+    if constexpr (G >= 2) pair_store(seg, m0 >> 1, (D[0] | (D[1] << 16)) ^ (F[0] | (F[1] << 16)));
+    if constexpr (G == 4) pair_store(seg, (m0 >> 1) + 1, (D[2] | (D[3] << 16)) ^ (F[2] | (F[3] << 16)));
+    if constexpr (G == 1) seg_at(seg, m0) = (uint16_t)(D[0] ^ F[0]);
 }
 
 // 1-D grid of blocks of kGaussWaves independent waves; block -> (run, group of kGaussWaves tiles):
