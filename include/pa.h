@@ -234,7 +234,10 @@ int pa_init_couplings(pa_run* runs, int n_runs, const int8_t* const* J_host);
  *         (field f = bits 16 (f mod 2) .. of word f/2);
  *   u48 = word0 | (word1 mod 2^16) << 32 of Philox(ctr (i, r, 2t+colour, 3));
  * t = step->t0 + s is the global sweep index, r the replica's index in the population.
- * Energies are updated with the spins. */
+ * Energies are updated with the spins.  Sizes: chains of any length; cubes of even side up
+ * to 20, and 24 and 32 (other sides: PA_ERR_ARG, nothing launched); Gaussian couplings: any
+ * size the buffers allow (tabled kernels for cube sides 4 and 8 and chains of 16k <= 1024 sites,
+ * one thread per replica otherwise). */
 int pa_sweep(pa_run* runs, int n_runs, const pa_step* step);
 
 /* Resample beta_from -> beta_to (Sec. II, eqs. Q and wn, Poisson copy numbers):

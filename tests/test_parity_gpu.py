@@ -179,6 +179,43 @@ def test_resample_parity(dim, L, layout, R0):
         assert close(rec[2], o.num_sites(dim, L) * math.log(2.0) + r["lnQ"])
 
 
+@pytest.mark.parametrize("L", [18, 20, 24, 32])
+@pytest.mark.parametrize("layout", ["bits64", "u8"])
+def test_largest_cubes_match_oracle(L, layout):
+    # the largest sides the library takes (the generic kernel; 32^3 = 32768 sites): initial
+    # population, two sweeps and a resample against the oracle
+    R0 = 70
+    note(f"largest cubes L={L} {layout}")
+    J = o.couplings(3, L, 3)
+    run = make_run(3, L, R0, layout, n_records=4)
+    so, Eo = o.init_population(3, L, J, 7, R0, capacity=run.capacity)
+    s, E = run.population()
+    assert np.array_equal(s, so[:R0]) and np.array_equal(E, Eo[:R0])
+    sched = pa.Schedule([0.0, 0.8, 1.0], 2, run.n_bins, device=DEV)
+    run.sweep(sched.step(1))
+    o.sweep(3, L, J, 7, 0.8, R0, so, Eo, 0, 2)
+    s, E = run.population()
+    assert np.array_equal(s, so[:R0]) and np.array_equal(E, Eo[:R0])
+    run.resample(sched.step(2))
+    r = o.resample(3, L, 7, 2, 0.8, 1.0, R0, R0, so, Eo, run.capacity)
+    assert r["status"] == 0 and run.query().R == r["R_new"]
+    s, E = run.population()
+    assert np.array_equal(s, r["s"][: r["R_new"]]) and np.array_equal(E, r["E"][: r["R_new"]])
+
+
+def test_unsupported_cube_side_is_rejected():
+    # even sides the buffers allow but no sweep kernel takes (22, 26, 28, 30): PA_ERR_ARG, the
+    # population untouched
+    note("unsupported cube side")
+    run = make_run(3, 22, 64, "bits64", n_records=4)
+    s0, E0 = run.population()
+    sched = pa.Schedule([0.0, 0.5], 2, run.n_bins, device=DEV)
+    with pytest.raises(pa.PAError):
+        run.sweep(sched.step(1))
+    s1, E1 = run.population()
+    assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
+
+
 def test_copy_numbers_in_the_hundreds():
     # one step of beta 0 -> 0.1 from the random start of 5000 replicas of the L = 8 cube: the lowest
     # energies get copy numbers up to ~700, i.e. many Poisson(64) blocks and every ladder level
