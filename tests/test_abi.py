@@ -14,6 +14,19 @@ from paper_1006_0252_amd import pa
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pa.h")
 
 
+def no_gpu():
+    """The descriptor tests below hand the library fake device addresses that its host checks must
+    refuse; they run only where no GPU could be reached if a check let one through."""
+    try:
+        import torch
+    except ImportError:
+        return True
+    return torch.cuda.device_count() == 0
+
+
+fake_pointers = pytest.mark.skipif(not no_gpu(), reason="fake device pointers: host checks only, run without a GPU")
+
+
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -89,6 +102,44 @@ def test_calls_reject_bad_runs_without_touching_the_device():
     assert pa.lib().pa_strerror(pa.PA_ERR_CAPACITY).startswith(b"resampled population")
 
 
+@fake_pointers
+def test_each_bad_descriptor_field_is_rejected_without_touching_the_device():
+    # a well-formed descriptor (aligned fake pointers, never dereferenced) with one field at a time
+    # set to a value the calls refuse: empty or oversized populations, capacities off the 64-replica
+    # grid, no records, unknown layouts and couplings, Gaussian bonds on bit-packed spins, lattices
+    # the library has no geometry for, a null buffer
+    base = 1 << 40
+
+    def good():
+        r = pa.pa_run()
+        r.dim, r.L, r.layout, r.n_records, r.capacity, r.R0, r.couplings = 3, 8, pa.PA_BITS64, 4, 128, 100, pa.PA_PM1
+        r.J, r.energy[0], r.energy[1], r.counts, r.offsets = base, base + 4096, base + 8192, base + 12288, base + 16384
+        r.work, r.record, r.state = base + 20480, base + 24576, base + 28672
+        r.spins[0], r.spins[1] = base + 32768, base + 65536
+        return r
+
+    bad = [("R0", 0), ("R0", -5), ("R0", 129), ("capacity", 0), ("capacity", 100), ("capacity", -64),
+           ("n_records", 0), ("layout", 7), ("couplings", 9), ("couplings", pa.PA_GAUSS), ("L", 7), ("L", 0),
+           ("dim", 2), ("dim", 0), ("J", None), ("state", None), ("work", None)]
+    step = pa.pa_step()
+    step.beta_from, step.beta_to, step.k, step.n_sweeps = 0.0, 0.1, 1, 1
+    L = pa.lib()
+    for field, value in bad:
+        r = good()
+        setattr(r, field, value)
+        for call in (L.pa_init_couplings, L.pa_measure):
+            assert call(ctypes.byref(r), 1, None) == pa.PA_ERR_ARG, (field, value, call)
+        for call in (L.pa_sweep, L.pa_resample):
+            assert call(ctypes.byref(r), 1, ctypes.byref(step)) == pa.PA_ERR_ARG, (field, value, call)
+    # and a bad step with a good descriptor
+    for field, value in (("k", 0), ("n_sweeps", -1), ("t0", -1), ("beta_from", -0.1), ("beta_to", float("nan"))):
+        st = pa.pa_step()
+        st.beta_from, st.beta_to, st.k, st.n_sweeps = 0.0, 0.1, 1, 1
+        setattr(st, field, value)
+        assert L.pa_sweep(ctypes.byref(good()), 1, ctypes.byref(st)) == pa.PA_ERR_ARG, (field, value)
+
+
+@fake_pointers
 def test_calls_reject_unaligned_buffers_without_touching_the_device():
     # a well-formed descriptor whose spin buffer is 8 bytes off a 256-byte boundary (the pointers
     # are never dereferenced: the check comes first)

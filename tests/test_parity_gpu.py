@@ -236,6 +236,42 @@ def test_copy_numbers_in_the_hundreds():
     assert np.array_equal(s, r["s"][: r["R_new"]]) and np.array_equal(E, r["E"][: r["R_new"]])
 
 
+@pytest.mark.parametrize("R0", [1, 63, 64, 65, 129])
+@pytest.mark.parametrize("L,layout", [(8, "u8"), (8, "bits64"), (16, "bits64")])
+def test_population_sizes_at_group_edges(L, layout, R0):
+    # a single replica, one short of a 64-replica group, exactly one group, one past it, two groups
+    # and one: initial population, two sweeps and a resample against the oracle (a population that
+    # dies out must be flagged on both sides and left as it was)
+    dim = 3
+    note(f"group edges L={L} {layout} R0={R0}")
+    J = o.couplings(dim, L, 3)
+    run = make_run(dim, L, R0, layout, n_records=4)
+    so, Eo = o.init_population(dim, L, J, 7, R0, capacity=run.capacity)
+    s, E = run.population()
+    assert np.array_equal(s, so[:R0]) and np.array_equal(E, Eo[:R0])
+    sched = pa.Schedule([0.0, 0.9, 1.0], 2, run.n_bins, device=DEV)
+    run.sweep(sched.step(1))
+    o.sweep(dim, L, J, 7, 0.9, R0, so, Eo, 0, 2)
+    s, E = run.population()
+    assert np.array_equal(s, so[:R0]) and np.array_equal(E, Eo[:R0])
+    r = o.resample(dim, L, 7, 2, 0.9, 1.0, R0, R0, so, Eo, run.capacity)
+    run.resample(sched.step(2))
+    if r["status"] == o.ERR_EXTINCT:
+        code, flags = run.status()
+        assert code == pa.PA_ERR_EXTINCT and flags & pa.PA_FLAG_EXTINCT
+        assert run.query().R == R0
+        s1, E1 = run.population()
+        assert np.array_equal(s1, s) and np.array_equal(E1, E)
+        return
+    assert r["status"] == 0
+    info = run.query()
+    assert info.status == 0 and info.R == r["R_new"]
+    c, off = run.counts_offsets(R0)
+    assert np.array_equal(c, r["counts"]) and np.array_equal(off, r["offsets"])
+    s, E = run.population()
+    assert np.array_equal(s, r["s"][: r["R_new"]]) and np.array_equal(E, r["E"][: r["R_new"]])
+
+
 RUN_CASES = [
     ("ring C1", 1, 64, "u8", 1000, 51, 5),
     ("ring C1 bits", 1, 64, "bits64", 1000, 51, 5),
