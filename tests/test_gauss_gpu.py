@@ -42,9 +42,11 @@ def test_couplings_and_initial_population(dim, L):
 
 
 # cubes of side 4 and 8 and chains of 16 k sites take the tabled kernel (ragged last tiles, several
-# blocks); side 6 and the chain of 40 take the per-replica kernel
+# blocks; a single replica; chains of an odd and an even number of 16-site segments); side 6 and the
+# chain of 40 take the per-replica kernel
 SWEEP_CASES = [(1, 16, 130, 0.7), (3, 4, 300, 0.7), (3, 4, 77, 3.0), (3, 6, 65, 0.0), (3, 6, 130, 1.3),
-               (3, 8, 1000, 0.7), (3, 8, 2100, 2.5), (3, 8, 64, 0.0), (1, 256, 300, 5.0), (1, 40, 90, 1.0)]
+               (3, 8, 1000, 0.7), (3, 8, 2100, 2.5), (3, 8, 64, 0.0), (1, 256, 300, 5.0), (1, 40, 90, 1.0),
+               (3, 8, 1, 1.0), (3, 4, 1, 1.0), (1, 48, 129, 0.9), (1, 32, 63, 0.9), (1, 1024, 70, 1.5)]
 
 
 @pytest.mark.parametrize("dim,L,R,beta", SWEEP_CASES)
