@@ -379,22 +379,33 @@ __global__ void __launch_bounds__(256) k_scan_down(pa_state* base)
     if (tile0 + kScanTile >= R && threadIdx.x == 0) st->offsets[R] = st->R_new;
 }
 
-// source replica of each new replica: largest j with offsets[j] <= r'
+// source replica of each new replica, a block per 256 consecutive sources: their offsets go to LDS,
+// and the block's new replicas offsets[j0] .. offsets[j0 + 256] - 1 each find their source there
+// (largest j with offsets[j] <= r', 8 LDS steps) and are written in order.  Per new replica over
+// the whole array, the same search took ~20 dependent global loads; per source, the writes of
+// uneven copy numbers were scattered and slower still.
 __global__ void __launch_bounds__(256) k_src(pa_state* base)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
-    const int64_t rn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (rn >= st->R_new) return;
-    const int64_t* off = st->offsets;
-    int64_t lo = 0, hi = st->R;  // invariant: off[lo] <= rn < off[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (off[mid] <= rn) lo = mid;
-        else hi = mid;
-    }
+    const int64_t R = st->R;
+    const int64_t j0 = (int64_t)blockIdx.x * 256;
+    if (j0 >= R) return;
+    const int n = (int)(R - j0 < 256 ? R - j0 : 256);
+    __shared__ int64_t off[257];
+    for (int i = threadIdx.x; i <= n; i += 256) off[i] = st->offsets[j0 + i];  // offsets[R] = R~'
+    __syncthreads();
+    const int64_t A = off[0], B = off[n];
     int32_t* src = work_ptr<int32_t>(st, work_layout(st->N, st->n_bins, st->capacity).src);
-    src[rn] = (int32_t)lo;
+    for (int64_t d = A + threadIdx.x; d < B; d += 256) {
+        int lo = 0, hi = n;  // off[lo] <= d < off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= d) lo = mid;
+            else hi = mid;
+        }
+        src[d] = (int32_t)(j0 + lo);
+    }
 }
 
 // u8 gather: one thread per 16 bytes of a destination row
