@@ -253,38 +253,94 @@ __device__ inline int64_t invert_ladder(int m, uint32_t u)
     return n;
 }
 
-// copy numbers: draw d of replica j at step k is word d mod 4 of Philox(d/4, j, k, 4)
+// Copy numbers: replica j's Poisson(lambda_j) count at step k is the sum of q Poisson(64) blocks and
+// a Poisson(2^m) count K thinned by K draws against keep = rem 2^(32 - m).  Draw d (blocks d = 0 ..
+// q - 1, K at d = q, the thinning draws at d = q + 1 ..) is word d mod 4 of Philox(d / 4, j, k, 4).
+// Light lanes (no blocks, 2^m < 16) draw in turn; the wave takes each heavy lane's draws
+// together, spread over its 64 lanes (the draws are counter-based, so any lane can make any of
+// them, and the count is an integer sum), instead of waiting for one lane to make them one by one.
+constexpr int kCopiesHeavyM = 4;
+
+struct CopyDraws {
+    uint32_t j, k, k0, k1;
+    __device__ uint32_t at(uint32_t d) const
+    {
+        return word_of(philox10(d >> 2, j, k, kTagPoisson, k0, k1), (int)(d & 3));
+    }
+};
+
+__device__ inline int64_t copies_light(const CopyDraws& cd, int m, uint64_t keep)
+{
+    uint32_t d = 0;
+    uint4v v = {0, 0, 0, 0};
+    auto draw = [&]() -> uint32_t {
+        if ((d & 3) == 0) v = philox10(d >> 2, cd.j, cd.k, kTagPoisson, cd.k0, cd.k1);
+        const uint32_t u = word_of(v, d & 3);
+        ++d;
+        return u;
+    };
+    const int64_t K = invert_ladder(m, draw());
+    int64_t n = 0;
+    for (int64_t e = 0; e < K; ++e)
+        if ((uint64_t)draw() < keep) ++n;
+    return n;
+}
+
+// every lane of the wave calls this (lanes without a replica with heavy = false); returns the
+// count of a heavy lane's replica, n unchanged elsewhere
+__device__ inline int64_t copies_heavy_by_wave(bool heavy, int64_t n, const CopyDraws& mine, int m, int64_t q,
+                                               uint64_t keep)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t todo = __ballot(heavy);
+    while (todo) {
+        const int h = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        CopyDraws cd = mine;
+        cd.j = (uint32_t)__shfl((int)mine.j, h, 64);
+        const int mh = __shfl(m, h, 64);
+        const int64_t qh = __shfl(q, h, 64);
+        const uint64_t keeph = (uint64_t)__shfl((int64_t)keep, h, 64);
+        int64_t part = 0;
+        for (int64_t blk = lane; blk < qh; blk += 64) part += invert_ladder(kLadderMax, cd.at((uint32_t)blk));
+        const int64_t K = invert_ladder(mh, cd.at((uint32_t)qh));
+        for (int64_t e = lane; e < K; e += 64)
+            if ((uint64_t)cd.at((uint32_t)(qh + 1 + e)) < keeph) ++part;
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (lane == h) n = part;
+    }
+    return n;
+}
+
 __global__ void __launch_bounds__(256) k_copies(pa_state* base, int32_t k)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= st->R) return;
+    const int64_t R = st->R;
+    if (j - (int64_t)(threadIdx.x & 63) >= R) return;  // the whole wave past R
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     const int64_t* bin_q = work_ptr<int64_t>(st, wl.bin_q);
     const uint64_t* bin_keep = work_ptr<uint64_t>(st, wl.bin_keep);
     const int32_t* bin_m = work_ptr<int32_t>(st, wl.bin_m);
-    const int b = (st->energy[st->cur][j] - st->E_base) >> 2;
-    const int m = bin_m[b];
-    int64_t n = 0;
-    if (m != 1000) {
-        const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
-        uint32_t d = 0;
-        uint4v v = {0, 0, 0, 0};
-        auto draw = [&]() -> uint32_t {
-            if ((d & 3) == 0) v = philox10(d >> 2, (uint32_t)j, (uint32_t)k, kTagPoisson, k0, k1);
-            const uint32_t u = word_of(v, d & 3);
-            ++d;
-            return u;
-        };
-        const int64_t q = bin_q[b];
-        for (int64_t blk = 0; blk < q; ++blk) n += invert_ladder(kLadderMax, draw());
-        const int64_t K = invert_ladder(m, draw());
-        const uint64_t keep = bin_keep[b];
-        for (int64_t e = 0; e < K; ++e)
-            if ((uint64_t)draw() < keep) ++n;
+    const bool live = j < R;
+    int m = 1000;  // bins of zero weight carry m = 1000: no copies
+    int64_t q = 0;
+    uint64_t keep = 0;
+    if (live) {
+        const int b = (st->energy[st->cur][j] - st->E_base) >> 2;
+        m = bin_m[b];
+        if (m != 1000) {
+            q = bin_q[b];
+            keep = bin_keep[b];
+        }
     }
-    st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
+    const CopyDraws cd = {(uint32_t)j, (uint32_t)k, (uint32_t)st->seed, (uint32_t)(st->seed >> 32)};
+    const bool drawn = live && m != 1000;
+    const bool heavy = drawn && (q > 0 || m >= kCopiesHeavyM);
+    int64_t n = drawn && !heavy ? copies_light(cd, m, keep) : 0;
+    n = copies_heavy_by_wave(heavy, n, cd, m, q, keep);
+    if (live) st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
 }
 
 // block sums of the copy numbers over tiles of kScanTile replicas
@@ -692,42 +748,38 @@ __global__ void k_gauss_normalise(pa_state* base, ResampleParams p)
     *reinterpret_cast<double*>(&misc[kMiscGaussS]) = S;
 }
 
+// copy numbers from the replica weights, drawn as in k_copies
 __global__ void __launch_bounds__(256) k_gauss_copies(pa_state* base, ResampleParams p)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= st->R) return;
+    const int64_t R = st->R;
+    if (j - (int64_t)(threadIdx.x & 63) >= R) return;  // the whole wave past R
     const int64_t* misc = work_ptr<int64_t>(st, work_layout(st->N, st->n_bins, st->capacity).misc);
     const double S = *reinterpret_cast<const double*>(&misc[kMiscGaussS]);
     const double* w = reinterpret_cast<const double*>(st->energy[st->cur ^ 1]);
     const double Rt = p.R_target > 0.0 ? p.R_target : (double)st->R0;
-    const double lam = (Rt * w[j]) / S;
-    int64_t n = 0;
+    const bool live = j < R;
+    const double lam = live ? (Rt * w[j]) / S : 0.0;
+    int m = kLadderMin;
+    int64_t q = 0;
+    uint64_t keep = 0;
     if (lam > 0.0) {
-        int64_t q = 0;
         double rem = lam;
         if (lam > 64.0) {
             q = (int64_t)ceil(lam / 64.0) - 1;
             rem = lam - 64.0 * (double)q;
         }
-        const int m = ladder_level(rem);
-        const uint64_t keep = (uint64_t)floor(ldexp(rem, 32 - m));
-        const uint32_t k0 = (uint32_t)st->seed, k1 = (uint32_t)(st->seed >> 32);
-        uint32_t d = 0;
-        uint4v v = {0, 0, 0, 0};
-        auto draw = [&]() -> uint32_t {
-            if ((d & 3) == 0) v = philox10(d >> 2, (uint32_t)j, (uint32_t)p.k, kTagPoisson, k0, k1);
-            const uint32_t u = word_of(v, d & 3);
-            ++d;
-            return u;
-        };
-        for (int64_t blk = 0; blk < q; ++blk) n += invert_ladder(kLadderMax, draw());
-        const int64_t K = invert_ladder(m, draw());
-        for (int64_t e = 0; e < K; ++e)
-            if ((uint64_t)draw() < keep) ++n;
+        m = ladder_level(rem);
+        keep = (uint64_t)floor(ldexp(rem, 32 - m));
     }
-    st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
+    const CopyDraws cd = {(uint32_t)j, (uint32_t)p.k, (uint32_t)st->seed, (uint32_t)(st->seed >> 32)};
+    const bool drawn = lam > 0.0;
+    const bool heavy = drawn && (q > 0 || m >= kCopiesHeavyM);
+    int64_t n = drawn && !heavy ? copies_light(cd, m, keep) : 0;
+    n = copies_heavy_by_wave(heavy, n, cd, m, q, keep);
+    if (live) st->counts[j] = (int32_t)min(n, (int64_t)INT32_MAX);
 }
 
 // runs: n runs with consecutive states on one stream (grid.y = run), or a single run
