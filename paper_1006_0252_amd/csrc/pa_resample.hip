@@ -719,25 +719,32 @@ __global__ void __launch_bounds__(256) k_gauss_weights(pa_state* base, double db
     w[j] = expd(-(dbeta * (E[j] - E_lo)));
 }
 
-// one thread per run: S in replica order, ln Q (the step's record is written by k_finish)
-__global__ void k_gauss_normalise(pa_state* base, ResampleParams p)
+// a block per run: S in replica order, ln Q (the step's record is written by k_finish).  The block
+// loads the weights a chunk at a time into LDS with coalesced loads, and one thread adds them in
+// order from there: the chain of dependent FP64 additions is then the cost (R = 2000: 22 us; from
+// global memory, one thread with eight loads ahead waited out the load latency every eight
+// additions: 50 us)
+constexpr int kNormChunk = 4096;
+
+__global__ void __launch_bounds__(256) k_gauss_normalise(pa_state* base, ResampleParams p)
 {
     pa_state* st = base + blockIdx.y;
     if (st->status) return;
+    __shared__ double chunk[kNormChunk];
     const WorkLayout wl = work_layout(st->N, st->n_bins, st->capacity);
     int64_t* misc = work_ptr<int64_t>(st, wl.misc);
     const double* w = reinterpret_cast<const double*>(st->energy[st->cur ^ 1]);
     const int64_t R = st->R;
     double S = 0.0;
-    int64_t j = 0;
-    for (; j + 8 <= R; j += 8) {  // the loads ahead of the (ordered) additions
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = w[j + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) S = S + v[u];
+    for (int64_t j0 = 0; j0 < R; j0 += kNormChunk) {
+        const int n = (int)(R - j0 < kNormChunk ? R - j0 : kNormChunk);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) chunk[i] = w[j0 + i];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 0; i < n; ++i) S = S + chunk[i];
+        __syncthreads();
     }
-    for (; j < R; ++j) S = S + w[j];
+    if (threadIdx.x != 0) return;
     const double dbeta = p.beta_to - p.beta_from;
     const double E_lo = *reinterpret_cast<const double*>(&misc[kMiscEmin]);
     if (!isfinite(S) || !(S > 0.0)) {
@@ -803,7 +810,7 @@ int launch_resample_gauss(const pa_run* runs, int n, const pa_step& step, hipStr
     const unsigned ny = (unsigned)n;
     hipLaunchKernelGGL(k_gauss_min, dim3(1, ny), dim3(256), 0, s, base);
     hipLaunchKernelGGL(k_gauss_weights, dim3(cap_blocks, ny), dim3(256), 0, s, base, step.beta_to - step.beta_from);
-    hipLaunchKernelGGL(k_gauss_normalise, dim3(1, ny), dim3(1), 0, s, base, p);
+    hipLaunchKernelGGL(k_gauss_normalise, dim3(1, ny), dim3(256), 0, s, base, p);
     hipLaunchKernelGGL(k_gauss_copies, dim3(cap_blocks, ny), dim3(256), 0, s, base, p);
     hipLaunchKernelGGL(k_scan_reduce, dim3(n_scan, ny), dim3(256), 0, s, base);
     hipLaunchKernelGGL(k_scan_top, dim3(1, ny), dim3(256), 0, s, base);
