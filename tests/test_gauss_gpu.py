@@ -66,18 +66,21 @@ def test_sweep_matches_oracle(dim, L, R, beta):
     assert np.array_equal(E, E_o)
 
 
-def test_copy_numbers_match_oracle():
-    note("gauss resample")
+# beta 0.3 -> 1.1: one replica takes 687 of the copies (ten Poisson(64) blocks); 0.3 -> 0.5: copy
+# numbers up to 87, 18 of them from Poisson(2^m >= 16) draws (the copies the whole wave draws)
+@pytest.mark.parametrize("b1", [1.1, 0.5])
+def test_copy_numbers_match_oracle(b1):
+    note(f"gauss resample 0.3 -> {b1}")
     R = 700
     run = gauss_run(3, 4, R, 8, 2, capacity=1536)
     run.sweep(pa.Schedule([0.0, 0.3], 2, run.n_bins, device=DEV).step(1))
-    run.resample(pa.Schedule([0.3, 1.1], 2, run.n_bins, device=DEV).step(1))
+    run.resample(pa.Schedule([0.3, b1], 2, run.n_bins, device=DEV).step(1))
     code, _ = run.status()
     assert code == pa.PA_OK
     J = o.couplings_gauss(3, 4, 2)
     s_o, E_o = o.init_replicas_gauss(3, 4, J, 8, 0, R)
     o.sweep_replicas_gauss(3, 4, J, 8, 0.3, 0, s_o, E_o, 0, 2)
-    st, counts_o, S_o, lnQ_o, E_lo_o = o.copy_numbers_gauss(8, 1, 0.3, 1.1, float(R), E_o)
+    st, counts_o, S_o, lnQ_o, E_lo_o = o.copy_numbers_gauss(8, 1, 0.3, b1, float(R), E_o)
     assert st == 0
     c, _ = run.counts_offsets(R)
     assert np.array_equal(c, counts_o)
