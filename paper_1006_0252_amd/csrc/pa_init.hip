@@ -66,17 +66,24 @@ __global__ void __launch_bounds__(256) k_init_bits64(const pa_state* __restrict_
     uint8_t* base = (uint8_t*)st->spins[0];
     int blk = -1;
     uint4v v = {0, 0, 0, 0};
-    for (int row = 0; row < NR; ++row) {
-        const int len = row_len(st, row);
-        uint32_t w = 0;
-        for (int x = 0; x < len; ++x) {
-            const int i = rowsites * row + x;
-            if ((i >> 7) != blk) {
-                blk = i >> 7;
-                v = philox10((uint32_t)blk, (uint32_t)r, 0u, kTagInit, k0, k1);
-            }
-            w |= ((word_of(v, (i & 127) >> 5) >> (i & 31)) & 1u) << x;
+    // word q of the replica's stream (spins 32 q .. 32 q + 31), the calls made in increasing order
+    auto word_at = [&](int q) -> uint32_t {
+        if ((q >> 2) != blk) {
+            blk = q >> 2;
+            v = philox10((uint32_t)blk, (uint32_t)r, 0u, kTagInit, k0, k1);
         }
+        return word_of(v, q & 3);
+    };
+    for (int row = 0; row < NR; ++row) {
+        // the row's spins are the len consecutive stream bits from i0: one word, or the top of one
+        // and the bottom of the next
+        const int len = row_len(st, row);
+        const int i0 = rowsites * row;
+        const int q0 = i0 >> 5, q1 = (i0 + len - 1) >> 5;
+        const uint32_t lo = word_at(q0);
+        const uint32_t hi = q1 != q0 ? word_at(q1) : 0u;
+        const uint32_t lm = len == 32 ? 0xFFFFFFFFu : (1u << len) - 1u;
+        uint32_t w = (uint32_t)(((((uint64_t)hi) << 32) | lo) >> (i0 & 31)) & lm;
         if (!valid) w = 0;
         const int64_t idx = ((r >> 6) * NR + row) * 64 + (r & 63);
         if (WB == 1) base[idx] = (uint8_t)w;
@@ -115,12 +122,36 @@ __global__ void __launch_bounds__(256) k_energy_u8(const pa_state* __restrict__ 
 __global__ void __launch_bounds__(256) k_energy_bits64(const pa_state* __restrict__ st, int buf)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= st->R) return;
-    const int L = st->L, N = st->N;
+    const int L = st->L;
     const int NR = n_rows_of(st);
     const int8_t* J = st->J;
     int neg = 0;
-    if (st->dim == 1) {
+    if (st->dim == 3) {
+        // the block first turns the couplings into sign masks per row and axis (bit x: J < 0 on the
+        // bond from site x + L row towards +axis), then each replica counts its unsatisfied bonds a
+        // row word at a time
+        __shared__ uint32_t jmask[3 * 32 * 32];
+        for (int e = threadIdx.x; e < 3 * NR; e += blockDim.x) {
+            const int row = e / 3, a = e - 3 * row;
+            uint32_t m = 0;
+            for (int x = 0; x < L; ++x) m |= (uint32_t)(J[3 * (x + L * row) + a] < 0) << x;
+            jmask[e] = m;
+        }
+        __syncthreads();
+        if (r >= st->R) return;
+        const uint32_t lm = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
+        for (int row = 0; row < NR; ++row) {
+            const int y = row % L, z = row / L;
+            const uint32_t own = load_row(st, buf, r, row) & lm;
+            const uint32_t yp = load_row(st, buf, r, (y + 1) % L + L * z) & lm;
+            const uint32_t zp = load_row(st, buf, r, y + L * ((z + 1) % L)) & lm;
+            const uint32_t sx = ((own >> 1) | (own << (L - 1))) & lm;  // bit x: site x + 1 (periodic)
+            neg += __popc(own ^ sx ^ jmask[3 * row]);
+            neg += __popc((own ^ yp ^ jmask[3 * row + 1]) & lm);
+            neg += __popc((own ^ zp ^ jmask[3 * row + 2]) & lm);
+        }
+    } else {
+        if (r >= st->R) return;
         for (int row = 0; row < NR; ++row) {
             const int len = row_len(st, row);
             const uint32_t own = load_row(st, buf, r, row);
@@ -132,23 +163,7 @@ __global__ void __launch_bounds__(256) k_energy_bits64(const pa_state* __restric
                 neg += (int)(si ^ sj ^ (uint32_t)(J[32 * row + x] < 0));
             }
         }
-    } else {
-        for (int row = 0; row < NR; ++row) {
-            const int y = row % L, z = row / L;
-            const uint32_t own = load_row(st, buf, r, row);
-            const uint32_t yp = load_row(st, buf, r, (y + 1) % L + L * z);
-            const uint32_t zp = load_row(st, buf, r, y + L * ((z + 1) % L));
-            for (int x = 0; x < L; ++x) {
-                const int i = x + L * row;
-                const uint32_t si = (own >> x) & 1u;
-                const uint32_t sx = (own >> ((x + 1) % L)) & 1u;
-                neg += (int)(si ^ sx ^ (uint32_t)(J[3 * i + 0] < 0));
-                neg += (int)(si ^ ((yp >> x) & 1u) ^ (uint32_t)(J[3 * i + 1] < 0));
-                neg += (int)(si ^ ((zp >> x) & 1u) ^ (uint32_t)(J[3 * i + 2] < 0));
-            }
-        }
     }
-    (void)N;
     st->energy[buf][r] = st->n_bonds - 2 * neg;
 }
 
