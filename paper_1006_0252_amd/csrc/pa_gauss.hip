@@ -183,10 +183,12 @@ __global__ void __launch_bounds__(64) k_sweep_gauss(const pa_state* __restrict__
 
 constexpr int kGaussWaves = 4;
 
-// h of site i for neighbour pattern b (bit a: neighbour a in field order has s_j != s_i)
-template <int NB>
-__device__ double gauss_field_pattern(const double* __restrict__ J, int i, int b, int L, int N)
+// h of site i for neighbour pattern b (bit a: neighbour a in field order has s_j != s_i); LC: the
+// cube side as a constant (its divisions become shifts), 0 for L at run time
+template <int NB, int LC = 0>
+__device__ double gauss_field_pattern(const double* __restrict__ J, int i, int b, int L_rt, int N)
 {
+    const int L = LC ? LC : L_rt;
     double h = 0.0;
     if constexpr (NB == 2) {
         const int im = i == 0 ? N - 1 : i - 1;
@@ -225,13 +227,13 @@ __device__ __forceinline__ uint64_t* gauss_table64(const pa_state* st)
     return reinterpret_cast<uint64_t*>(gauss_table(st) + ((size_t)st->N << NB));
 }
 
-// grid (entries / 256, runs): entry e = (c, m, b, k) of run blockIdx.y
-template <int NB>
+// grid (entries / 256, runs): entry e = (c, m, b, k) of run blockIdx.y; LC as in gauss_field_pattern
+template <int NB, int LC>
 __global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ states, double beta)
 {
     const pa_state* st = states + blockIdx.y;
     if (st->status) return;
-    const int N = st->N, L = st->L;
+    const int N = st->N, L = LC ? LC : st->L;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (N << NB)) return;
     const int half = (N / 2) << NB;
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(256) k_gauss_table(pa_state* __restrict__ stat
     const int col0 = NB == 2 ? 0 : ((i0 % L) + (i0 / L) % L + i0 / (L * L)) & 1;
     const int i = i0 + (col0 != c);
     uint64_t T64 = 0;
-    const bool always = gauss_threshold(gauss_field_pattern<NB>(reinterpret_cast<const double*>(st->J), i, b, L, N),
+    const bool always = gauss_threshold(gauss_field_pattern<NB, LC>(reinterpret_cast<const double*>(st->J), i, b, L, N),
                                         beta, &T64);
     if (always) T64 = ~0ull;
     gauss_table(st)[e] = (uint16_t)(T64 >> 48);
@@ -784,8 +786,9 @@ int launch_sweep_gauss(const pa_run* runs, int n_runs, bool consecutive, const p
     const size_t lds = (size_t)kGaussWaves * ((N / 16 + 1) / 2) * 64 * 4;
     auto go = [&](pa_state* base, int n, int64_t capacity, hipStream_t str) {
         const dim3 tgrid((unsigned)(((N << NB) + 255) / 256), (unsigned)n);
-        if (NB == 2) hipLaunchKernelGGL(k_gauss_table<2>, tgrid, dim3(256), 0, str, base, step.beta_to);
-        else hipLaunchKernelGGL(k_gauss_table<6>, tgrid, dim3(256), 0, str, base, step.beta_to);
+        if (NB == 2) hipLaunchKernelGGL((k_gauss_table<2, 0>), tgrid, dim3(256), 0, str, base, step.beta_to);
+        else if (L == 4) hipLaunchKernelGGL((k_gauss_table<6, 4>), tgrid, dim3(256), 0, str, base, step.beta_to);
+        else hipLaunchKernelGGL((k_gauss_table<6, 8>), tgrid, dim3(256), 0, str, base, step.beta_to);
         int st = hip_status(hipGetLastError());
         if (st != PA_OK) return st;
         const int groups = (int)((capacity / 64 + kGaussWaves - 1) / kGaussWaves);
