@@ -316,6 +316,55 @@ def test_full_run_parity(name, dim, L, layout, R0, nT, ns):
     assert close(float(fe.cpu()[0]), rec_o[-1, 3])
 
 
+def seeded_run_configs(n, seed=20261203):
+    """Whole-run configurations drawn from a fixed seed: every lattice shape the sweep kernels
+    specialise (cube sides 2-16, rings of 16-256 sites), both layouts, uneven populations and
+    schedules of uneven beta steps reaching every first-look regime."""
+    g = np.random.default_rng(seed)
+    out = []
+    for c in range(n):
+        if g.random() < 0.7:
+            dim, L = 3, int(g.choice([2, 4, 6, 8, 10, 12, 14, 16]))
+        else:
+            dim, L = 1, int(g.choice([16, 64, 100, 256]))
+        layout = str(g.choice(["u8", "bits64"]))
+        R0 = int(g.integers(20, 600))
+        nT = int(g.integers(3, 7))
+        ns = int(g.integers(1, 5))
+        steps = g.uniform(0.05, 1.0, nT - 1)
+        betas = [0.0] + list(np.cumsum(steps / steps.sum() * g.uniform(0.5, 4.0)))
+        out.append((c, dim, L, layout, R0, [float(b) for b in betas], ns, int(g.integers(1, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("c,dim,L,layout,R0,betas,ns,seed", seeded_run_configs(20))
+def test_seeded_random_runs_match_oracle(c, dim, L, layout, R0, betas, ns, seed):
+    note(f"seeded run {c}: dim={dim} L={L} {layout} R0={R0} nT={len(betas)} ns={ns} seed={seed}")
+    nT = len(betas)
+    dseed = seed ^ 0x5A5A
+    run = pa.Run(dim, L, R0, seed, dseed, n_records=nT, layout=layout, device=DEV)
+    run.init()
+    sched = pa.Schedule(betas, ns, run.n_bins, device=DEV)
+    for k in range(1, nT):
+        st = sched.step(k)
+        run.resample(st)
+        run.sweep(st)
+        pa.measure([run])
+    J = o.couplings(dim, L, dseed)
+    st_o, rec_o, s_o, E_o = o.run(dim, L, J, seed, R0, betas, ns, capacity=run.capacity)
+    assert st_o == 0
+    code, flags = run.status()
+    assert code == pa.PA_OK and flags == 0
+    rec = run.records()
+    for k in range(nT):
+        assert rec[k, 4] == rec_o[k, 1], f"R differs at k={k}"
+        assert close(rec[k, 1], rec_o[k, 2]) and close(rec[k, 2], rec_o[k, 3]), f"ln Q or -beta F differs at k={k}"
+        if k > 0:
+            assert rec[k, 6] == rec_o[k, 4], f"E mean differs at k={k}"
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+
+
 @pytest.mark.parametrize("dim,L,layout", [(1, 64, "u8"), (3, 8, "bits64"), (3, 6, "u8"), (3, 16, "bits64")])
 def test_overlap_parity(dim, L, layout):
     note(f"overlap dim={dim} L={L} {layout}")
