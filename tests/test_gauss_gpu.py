@@ -127,6 +127,50 @@ def test_whole_run_matches_oracle(dim, L, R0, nT):
     assert abs(fe.item() - rec_o[-1, 3]) <= 1e-12 * abs(rec_o[-1, 3])
 
 
+def seeded_gauss_configs(n, seed=1203):
+    """Whole Gaussian runs drawn from a fixed seed: the tabled shapes (cube sides 4 and 8, chains of
+    one, two, three and sixteen 16-site segments) and the per-replica ones (side 6, a chain of 40),
+    uneven populations and schedules of uneven beta steps."""
+    g = np.random.default_rng(seed)
+    shapes = [(3, 4), (3, 8), (3, 6), (1, 16), (1, 32), (1, 48), (1, 256), (1, 40)]
+    out = []
+    for c in range(n):
+        dim, L = shapes[int(g.integers(len(shapes)))]
+        R0 = int(g.integers(20, 500))
+        nT = int(g.integers(3, 7))
+        steps = g.uniform(0.05, 1.0, nT - 1)
+        betas = [0.0] + [float(b) for b in np.cumsum(steps / steps.sum() * g.uniform(0.5, 3.0))]
+        out.append((c, dim, L, R0, betas, int(g.integers(1, 4)), int(g.integers(1, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("c,dim,L,R0,betas,ns,seed", seeded_gauss_configs(12))
+def test_seeded_random_gauss_runs_match_oracle(c, dim, L, R0, betas, ns, seed):
+    note(f"seeded gauss run {c}: dim={dim} L={L} R0={R0} nT={len(betas)} ns={ns} seed={seed}")
+    nT = len(betas)
+    ds = seed ^ 0x3C3C
+    cap = int(np.ceil(R0 * 1.6 / 64)) * 64
+    run = gauss_run(dim, L, R0, seed, ds, n_records=nT, capacity=cap)
+    sched = pa.Schedule(betas, ns, run.n_bins, device=DEV)
+    for k in range(1, nT):
+        st = sched.step(k)
+        run.resample(st)
+        run.sweep(st)
+        pa.measure([run])
+    code, _ = run.status()
+    assert code == pa.PA_OK
+    J = o.couplings_gauss(dim, L, ds)
+    st_o, rec_o, s_o, E_o = o.run_gauss(dim, L, J, seed, R0, betas, ns, capacity=cap)
+    assert st_o == 0
+    s, E = run.population()
+    assert np.array_equal(s, s_o) and np.array_equal(E, E_o)
+    rec = run.records()
+    assert np.array_equal(rec[:, 4], rec_o[:, 1])
+    for k in range(nT):
+        assert abs(rec[k, 1] - rec_o[k, 2]) <= 1e-12 * max(1.0, abs(rec_o[k, 2])), k
+        assert abs(rec[k, 2] - rec_o[k, 3]) <= 1e-12 * max(1.0, abs(rec_o[k, 3])), k
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_matches_oracle(graph):
     # one launch per kernel over four consecutive runs (two realizations, pairs (0,1) and (2,3)),
