@@ -77,6 +77,47 @@ def test_batch_equals_solo_mixed_sizes(layout):
     assert np.allclose(fe.cpu().numpy(), rec[:, -1, 2], rtol=1e-15)
 
 
+def seeded_batches(n, seed=4242):
+    """Batches drawn from a fixed seed: 2-10 runs in pairs (overlap partners share the lattice and
+    couplings), mixed cube sides 2-16, populations of 1-400 replicas, both layouts."""
+    g = np.random.default_rng(seed)
+    out = []
+    for c in range(n):
+        n_pairs = int(g.integers(1, 6))
+        specs = []
+        for p in range(n_pairs):
+            L = int(g.choice([2, 4, 6, 8, 10, 12, 14, 16]))
+            for h in range(2):
+                specs.append(dict(dim=3, L=L, R0=int(g.integers(1, 400)), seed=int(g.integers(1, 1 << 30)),
+                                  disorder_seed=int(g.integers(1, 1 << 30)) if h == 0 else None))
+            specs[-1]["disorder_seed"] = specs[-2]["disorder_seed"]
+        out.append((c, str(g.choice(["bits64", "u8"])), specs))
+    return out
+
+
+@pytest.mark.parametrize("c,layout,specs", seeded_batches(6))
+def test_seeded_batches_equal_solo(c, layout, specs):
+    nT, ns = 5, 2
+    betas = [3.0 * k / (nT - 1) for k in range(nT)]
+    note(f"seeded batch {c}: {layout}, L {[sp['L'] for sp in specs]}, R0 {[sp['R0'] for sp in specs]}")
+    batch = pa.Batch(specs, nT, layout=layout, device=DEV).init()
+    solos = solo_runs(specs, nT, layout, [r.capacity for r in batch.runs])
+    n_bins = max(r.n_bins for r in batch.runs)
+    sched = pa.Schedule(betas, ns, n_bins, device=DEV)
+    for k in range(1, nT):
+        batch.step(sched, k, pairs=True)
+        st = sched.step(k)
+        for r in solos:
+            r.resample(st)
+            r.sweep(st)
+        pa.measure(solos, [i ^ 1 for i in range(len(solos))])
+    code, flags = batch.status()
+    solo_flags = [r.status() for r in solos]
+    if code == pa.PA_OK:
+        assert all(sc == pa.PA_OK for sc, _ in solo_flags)
+    compare(batch, solos, nT - 1)
+
+
 def test_batch_matches_oracle():
     specs = [dict(dim=3, L=6, R0=150, seed=31, disorder_seed=4), dict(dim=3, L=10, R0=90, seed=32, disorder_seed=5),
              dict(dim=3, L=8, R0=130, seed=33, disorder_seed=4)]
