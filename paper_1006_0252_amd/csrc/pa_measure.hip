@@ -93,23 +93,56 @@ __global__ void __launch_bounds__(256) k_overlap_u8(pa_state* base, const pa_sta
     }
 }
 
-// Hamming distance, bit-packed layout: lane = pair, loop over row words
+// Hamming distances of a 64-replica group g of runs A and B, bit-packed layout, one wave: each lane
+// loads a 16-byte piece (E replicas' words of one row) of both runs per row it takes, so a row of
+// the group is LPR lanes and a pass RPP rows, adds the popcount of each replica's xor word, and the
+// RPP lanes of the same piece then add their counts.  (One lane per replica with a load per row
+// word issued 16 times as many narrow loads.)  The distances are counted in hloc (LDS) or qh.
 template <typename Wt>
-__device__ inline int hamming_rows(const pa_state* a, const pa_state* b, int64_t j, int n_rows)
+__device__ inline void group_distances(const pa_state* a, const pa_state* b, int64_t g, int n_rows, int64_t P,
+                                       bool local, uint32_t* hloc, int64_t* qh)
 {
-    const Wt* x = (const Wt*)a->spins[a->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
-    const Wt* y = (const Wt*)b->spins[b->cur] + ((j >> 6) * n_rows) * 64 + (j & 63);
-    int d = 0;
-    for (int rho = 0; rho < n_rows; ++rho) d += __popc((uint32_t)(x[(int64_t)rho * 64] ^ y[(int64_t)rho * 64]));
-    return d;
+    constexpr int E = 16 / (int)sizeof(Wt);  // replicas per piece
+    constexpr int LPR = 64 / E;              // lanes per row
+    constexpr int RPP = 64 / LPR;            // rows per pass
+    constexpr int PER = 4 / (int)sizeof(Wt);  // replicas per 32-bit word of a piece
+    const int lane = (int)(threadIdx.x & 63), rr = lane / LPR, c = lane % LPR;
+    const uint4* A = reinterpret_cast<const uint4*>((const Wt*)a->spins[a->cur] + g * n_rows * 64);
+    const uint4* B = reinterpret_cast<const uint4*>((const Wt*)b->spins[b->cur] + g * n_rows * 64);
+    uint32_t cnt[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) cnt[e] = 0;
+    for (int row = rr; row < n_rows; row += RPP) {
+        const uint4 x = A[row * LPR + c], y = B[row * LPR + c];
+        const uint32_t w[4] = {x.x ^ y.x, x.y ^ y.y, x.z ^ y.z, x.w ^ y.w};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t v = w[e / PER] >> (8 * (int)sizeof(Wt) * (e % PER));
+            cnt[e] += (uint32_t)__popc(sizeof(Wt) == 4 ? v : v & ((1u << (8 * sizeof(Wt))) - 1u));
+        }
+    }
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < E; ++e) cnt[e] += (uint32_t)__shfl_xor((int)cnt[e], off, 64);
+    if (rr == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t j = g * 64 + c * E + e;
+            if (j < P) {
+                if (local) atomicAdd(&hloc[cnt[e]], 1u);
+                else atomicAdd((unsigned long long*)&qh[cnt[e]], 1ull);
+            }
+        }
+    }
 }
 
-// Hamming distance of replica j of runs A and B (pair_xor: B is A's partner run in the batch), one
-// thread per replica, kOverlapItems replicas per thread of a block.  The block counts its distances
-// in an LDS histogram (cap entries, when N + 1 fits) and adds its non-zero bins to the run's
-// histogram: the distances of a population sit within a few sqrt(N) of a few values, so one
-// global atomic per replica would serialise on a handful of addresses.
-constexpr int kOverlapItems = 4;
+// Hamming distance of replica j of runs A and B (pair_xor: B is A's partner run in the batch), a
+// wave per 64-replica group, four groups per block.  The block counts its distances in an LDS
+// histogram (cap entries, when N + 1 fits) and adds its non-zero bins to the run's histogram: the
+// distances of a population sit within a few sqrt(N) of a few values, so one global atomic per
+// replica would serialise on a handful of addresses.
+constexpr int kOverlapGroups = 4;
 
 __global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_state* b_given, int pair_xor, int cap)
 {
@@ -123,20 +156,18 @@ __global__ void __launch_bounds__(256) k_overlap_bits(pa_state* base, const pa_s
     const int n_rows = a->dim == 1 ? (a->N + 31) / 32 : a->L * a->L;
     const int WB = a->dim == 1 ? 4 : (a->L <= 8 ? 1 : (a->L <= 16 ? 2 : 4));
     int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+    const int64_t g0 = (int64_t)blockIdx.x * kOverlapGroups;
+    if (g0 * 64 >= P) return;  // the same for the whole block
     const bool local = N + 1 <= cap;
     if (local) {
         for (int d = threadIdx.x; d <= N; d += blockDim.x) hloc[d] = 0;
         __syncthreads();
     }
-    const int64_t j0 = (int64_t)blockIdx.x * blockDim.x * kOverlapItems;
-    const int64_t j1 = min(P, j0 + (int64_t)blockDim.x * kOverlapItems);
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-        int d;
-        if (WB == 1) d = hamming_rows<uint8_t>(a, b, j, n_rows);
-        else if (WB == 2) d = hamming_rows<uint16_t>(a, b, j, n_rows);
-        else d = hamming_rows<uint32_t>(a, b, j, n_rows);
-        if (local) atomicAdd(&hloc[d], 1u);
-        else atomicAdd((unsigned long long*)&qh[d], 1ull);
+    const int64_t g = g0 + (threadIdx.x >> 6);
+    if (g * 64 < P) {  // the same for the whole wave
+        if (WB == 1) group_distances<uint8_t>(a, b, g, n_rows, P, local, hloc, qh);
+        else if (WB == 2) group_distances<uint16_t>(a, b, g, n_rows, P, local, hloc, qh);
+        else group_distances<uint32_t>(a, b, g, n_rows, P, local, hloc, qh);
     }
     if (local) {
         __syncthreads();
@@ -218,7 +249,7 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
         else {
             // LDS histogram of up to 8192 bins (every cube; longer chains count in global memory)
             const int cap = N + 1 <= 8192 ? (int)(N + 1) : 0;
-            const int64_t per_block = 256 * kOverlapItems;
+            const int64_t per_block = 64 * kOverlapGroups;
             hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + per_block - 1) / per_block), n), dim3(256),
                                (size_t)cap * 4, s, base, bg, pair_xor, cap);
         }
