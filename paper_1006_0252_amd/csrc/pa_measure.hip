@@ -59,37 +59,60 @@ __global__ void k_qhist_clear(pa_state* base)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= st->N; i += gridDim.x * blockDim.x) qh[i] = 0;
 }
 
-// Hamming distance of replica j of run A and replica j of run B, u8 layout
-__global__ void __launch_bounds__(256) k_overlap_u8(pa_state* base, const pa_state* b_given, int pair_xor)
+// Hamming distances, one byte per spin: a wave per replica pair (its lanes over 16-byte pieces of the
+// rows, then a wave sum), kOverlapU8Items pairs per wave in turn; the block counts its distances in
+// an LDS histogram (cap entries, when N + 1 fits) and adds the non-zero bins to the run's
+// histogram (one global atomic per pair serialised on the few bins a population's distances take)
+constexpr int kOverlapU8Items = 8;
+
+__global__ void __launch_bounds__(256) k_overlap_u8(pa_state* base, const pa_state* b_given, int pair_xor, int cap)
 {
+    extern __shared__ uint32_t hloc[];
     if (pair_xor && (blockIdx.y & 1)) return;  // a pair's distances are counted once, by its first run
     pa_state* a = base + blockIdx.y;
     const pa_state* b = pair_xor ? base + (blockIdx.y ^ 1) : b_given;
     if (a->status || b->status) return;
     const int64_t P = min(a->R, b->R);
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (j >= P) return;
+    const int64_t j0 = (int64_t)blockIdx.x * 4 * kOverlapU8Items;
+    if (j0 >= P) return;  // the same for the whole block
     const int stride = a->row_stride, N = a->N;
-    const uint8_t* x = (const uint8_t*)a->spins[a->cur] + j * stride;
-    const uint8_t* y = (const uint8_t*)b->spins[b->cur] + j * stride;
-    int d = 0;
-    for (int i = lane * 16; i < N; i += 64 * 16) {
-        const uint4 u = *(const uint4*)(x + i);
-        const uint4 v = *(const uint4*)(y + i);
-        // bytes past N are padding: zero in both rows only if never written, so mask them
-        uint32_t w[4] = {u.x ^ v.x, u.y ^ v.y, u.z ^ v.z, u.w ^ v.w};
-        const int valid = min(16, N - i);
-        for (int k = 0; k < 4; ++k) {
-            const int vb = valid - 4 * k;
-            const uint32_t m = vb >= 4 ? 0xFFFFFFFFu : (vb <= 0 ? 0u : ((1u << (8 * vb)) - 1u));
-            d += __popc(w[k] & m & 0x01010101u);
+    const bool local = N + 1 <= cap;
+    int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
+    if (local) {
+        for (int d = threadIdx.x; d <= N; d += blockDim.x) hloc[d] = 0;
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    for (int it = 0; it < kOverlapU8Items; ++it) {
+        const int64_t j = j0 + (int64_t)(threadIdx.x >> 6) * kOverlapU8Items + it;
+        if (j >= P) break;  // the same for the whole wave
+        const uint8_t* x = (const uint8_t*)a->spins[a->cur] + j * stride;
+        const uint8_t* y = (const uint8_t*)b->spins[b->cur] + j * stride;
+        int d = 0;
+        for (int i = lane * 16; i < N; i += 64 * 16) {
+            const uint4 u = *(const uint4*)(x + i);
+            const uint4 v = *(const uint4*)(y + i);
+            // bytes past N are padding: zero in both rows only if never written, so mask them
+            uint32_t w[4] = {u.x ^ v.x, u.y ^ v.y, u.z ^ v.z, u.w ^ v.w};
+            const int valid = min(16, N - i);
+            for (int k = 0; k < 4; ++k) {
+                const int vb = valid - 4 * k;
+                const uint32_t m = vb >= 4 ? 0xFFFFFFFFu : (vb <= 0 ? 0u : ((1u << (8 * vb)) - 1u));
+                d += __popc(w[k] & m & 0x01010101u);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        if (lane == 0) {
+            if (local) atomicAdd(&hloc[d], 1u);
+            else atomicAdd((unsigned long long*)&qh[d], 1ull);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if (lane == 0) {
-        int64_t* qh = work_ptr<int64_t>(a, work_layout(a->N, a->n_bins, a->capacity).qhist);
-        atomicAdd((unsigned long long*)&qh[d], 1ull);
+    if (local) {
+        __syncthreads();
+        for (int d = threadIdx.x; d <= N; d += blockDim.x) {
+            const uint32_t c = hloc[d];
+            if (c) atomicAdd((unsigned long long*)&qh[d], (unsigned long long)c);
+        }
     }
 }
 
@@ -244,11 +267,13 @@ int launch_measure(const pa_run* runs, int n, const pa_run* partner, int pair_xo
         hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), n), dim3(256), 0, s, base);
         // the partner's population must be final before it is read: both runs on the same stream,
         // or the partner's stream joined by the caller
-        if (runs[0].layout == PA_U8)
-            hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
-        else {
-            // LDS histogram of up to 8192 bins (every cube; longer chains count in global memory)
-            const int cap = N + 1 <= 8192 ? (int)(N + 1) : 0;
+        // LDS histogram of up to 8192 bins (every cube; longer chains count in global memory)
+        const int cap = N + 1 <= 8192 ? (int)(N + 1) : 0;
+        if (runs[0].layout == PA_U8) {
+            const int64_t per_block = 4 * kOverlapU8Items;
+            hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + per_block - 1) / per_block), n), dim3(256),
+                               (size_t)cap * 4, s, base, bg, pair_xor, cap);
+        } else {
             const int64_t per_block = 64 * kOverlapGroups;
             hipLaunchKernelGGL(k_overlap_bits, dim3((unsigned)((P + per_block - 1) / per_block), n), dim3(256),
                                (size_t)cap * 4, s, base, bg, pair_xor, cap);
@@ -272,7 +297,10 @@ int launch_measure_gauss(const pa_run* runs, int n, const pa_run* partner, int p
     pa_state* base = runs[0].state;
     const pa_state* bg = partner ? partner->state : nullptr;
     hipLaunchKernelGGL(k_qhist_clear, dim3((unsigned)((N + 256) / 256), n), dim3(256), 0, s, base);
-    hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + 3) / 4), n), dim3(256), 0, s, base, bg, pair_xor);
+    const int cap = N + 1 <= 8192 ? (int)(N + 1) : 0;
+    const int64_t per_block = 4 * kOverlapU8Items;
+    hipLaunchKernelGGL(k_overlap_u8, dim3((unsigned)((P + per_block - 1) / per_block), n), dim3(256),
+                       (size_t)cap * 4, s, base, bg, pair_xor, cap);
     hipLaunchKernelGGL(k_overlap_stats, dim3(1, n), dim3(256), 0, s, base, bg, pair_xor);
     return hip_status(hipGetLastError());
 }
