@@ -114,6 +114,11 @@ __global__ void __launch_bounds__(256) k_hist(pa_state* base, int cap_bins)
     const int nb = st->n_bins;
     const bool priv = nb <= cap_bins;
     const int64_t R = st->R;
+    // a run takes only the blocks its energies fill (kHistLoads per thread): in a batch, a small
+    // run left the rest to clear, scan and merge a histogram each for a few energies
+    const int64_t per_block = (int64_t)blockDim.x * kHistLoads;
+    const int nblk = (int)min((int64_t)gridDim.x, (R + per_block - 1) / per_block);
+    if ((int)blockIdx.x >= nblk) return;  // the same for the whole block
     const int32_t* E = st->energy[st->cur];
     const int Eb = st->E_base;
     if (priv)
@@ -122,7 +127,7 @@ __global__ void __launch_bounds__(256) k_hist(pa_state* base, int cap_bins)
     int emin = INT32_MAX, emax = INT32_MIN;
     // kHistLoads energies per thread are loaded before any of them is counted, so that many loads
     // are in flight at once (a load and its count in turn wait out the memory latency each time)
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)nblk * blockDim.x;
     for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j0 < R; j0 += kHistLoads * stride) {
         int e[kHistLoads];
 #pragma unroll
